@@ -1,0 +1,359 @@
+"""Plain FP64 CPU oracle for fast count sketch (FCS).
+
+TEST INFRASTRUCTURE ONLY.  This module is imported by ``tests/``, by the
+``smoke()`` check of ``__graft_entry__`` and by the CPU-baseline leg of
+``bench.py``.  The product path (the HIP library and its Python binding) never
+imports, links or calls anything under ``oracle/``, and this module imports
+nothing from the product path.
+
+Everything here is written from the paper (Cao and Liu, "Efficient Tensor
+Contraction via Fast Count Sketch", arXiv 2106.13062) in its own order and
+notation, with 0-based indices:
+
+* mode sizes I_n, hash lengths J_n, n = 0..N-1;
+* J~ = sum_n J_n - N + 1 (Definition 4);
+* the bin of the multi-index (i_0..i_{N-1}) is H = sum_n h_n(i_n) in [0, J~),
+  which is the paper's 1-based h_{N+1} = sum h_n - N + 1 shifted down by one;
+* its sign is S = prod_n s_n(i_n);
+* vec(T) is column-major: mode 0 varies fastest (Section 2.1).
+
+All arithmetic is float64 (inputs given in float32 are upcast first).  Where
+the method reaches a result that has a plain definition, the function below is
+that definition written out; library primitives used as single steps are
+``numpy.bincount`` / ``numpy.add.at`` (scatter-add), ``numpy.convolve``,
+``numpy.correlate``, ``numpy.fft`` and ``numpy.median``.
+
+Parity status of each function (what pins it is in ``tests/test_oracle_*.py``):
+
+* ``hash_tables``        pinned by the published SplitMix64 known-answer
+                          sequence plus statistical checks; the *choice* of
+                          hash family is a reading (the paper only asks for
+                          2-wise independence) and is otherwise parity unpinned.
+* ``count_sketch``       pinned by an explicit loop over Definition 1.
+* ``fcs_dense``/``fcs_coo`` pinned by a hand-worked example, unit impulses,
+                          N = 1 == count sketch, the TS fold and HCS
+                          anti-diagonal relations, and linearity.
+* ``fcs_cp_conv``/``fcs_cp_fft`` pinned against ``fcs_dense`` of the
+                          materialised CP tensor (the identity of Section 3.1).
+* ``inner`` / ``median`` pinned by exact enumeration of all hash functions on
+                          tiny shapes (Proposition 1 unbiasedness) and by the
+                          order-statistic definition of the median.
+* ``contract_free``      pinned against the literal inner product with the
+                          brute-force sketch of e_i o u o v (Section 4.1).
+* ``kron_fcs``           pinned against ``fcs_dense`` of the materialised
+                          order-4 tensor (Section 4.3).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+# ---------------------------------------------------------------------------
+# Hash functions (Definitions 1-4 ask for 2-wise independent pairs h_n, s_n;
+# the family is not specified).  Reading used here: one SplitMix64 stream per
+# (sketch d, mode n), keyed from a single plan seed.
+#   mix(x)    = SplitMix64 finaliser of (x + golden gamma), all mod 2^64
+#   key(d, n) = mix(mix(seed) + d * 2^16 + n)
+#   y         = mix(key(d, n) + i)
+#   h_n(i)    = ((y >> 32) * J_n) >> 32      (Lemire multiply-shift range map)
+#   s_n(i)    = +1 if the low bit of y is 0, else -1
+# SplitMix64: G. Steele, D. Lea, C. Flood, "Fast splittable pseudorandom
+# number generators", OOPSLA 2014.
+# ---------------------------------------------------------------------------
+MASK64 = (1 << 64) - 1
+GOLDEN_GAMMA = 0x9E3779B97F4A7C15
+MIX_C1 = 0xBF58476D1CE4E5B9
+MIX_C2 = 0x94D049BB133111EB
+
+
+def mix64(x: int) -> int:
+    """SplitMix64 output for a generator whose state is ``x`` before the step."""
+    z = (x + GOLDEN_GAMMA) & MASK64
+    z = ((z ^ (z >> 30)) * MIX_C1) & MASK64
+    z = ((z ^ (z >> 27)) * MIX_C2) & MASK64
+    return z ^ (z >> 31)
+
+
+def _mix64_array(x: np.ndarray) -> np.ndarray:
+    """Same as ``mix64`` on a uint64 array (numpy wraps mod 2^64)."""
+    x = x.astype(np.uint64, copy=False)
+    z = x + np.uint64(GOLDEN_GAMMA)
+    z = (z ^ (z >> np.uint64(30))) * np.uint64(MIX_C1)
+    z = (z ^ (z >> np.uint64(27))) * np.uint64(MIX_C2)
+    return z ^ (z >> np.uint64(31))
+
+
+def splitmix64_sequence(seed: int, count: int) -> list[int]:
+    """The first ``count`` outputs of a SplitMix64 generator seeded with ``seed``."""
+    out, state = [], seed & MASK64
+    for _ in range(count):
+        out.append(mix64(state))
+        state = (state + GOLDEN_GAMMA) & MASK64
+    return out
+
+
+def hash_key(seed: int, d: int, n: int) -> int:
+    return mix64((mix64(seed & MASK64) + (d << 16) + n) & MASK64)
+
+
+def hash_pair(seed: int, d: int, n: int, I_n: int, J_n: int):
+    """(h_n, s_n) of sketch d: h in [0, J_n) as int64, s in {+1, -1} as int8."""
+    key = hash_key(seed, d, n)
+    i = np.arange(I_n, dtype=np.uint64)
+    y = _mix64_array(np.uint64(key) + i)
+    h = ((y >> np.uint64(32)) * np.uint64(J_n)) >> np.uint64(32)
+    s = np.where((y & np.uint64(1)) == 0, 1, -1).astype(np.int8)
+    return h.astype(np.int64), s
+
+
+def hash_tables(seed: int, D: int, I, J):
+    """Per-sketch, per-mode hash pairs: ``h[d][n]``, ``s[d][n]``."""
+    hs, ss = [], []
+    for d in range(D):
+        hd, sd = [], []
+        for n, (I_n, J_n) in enumerate(zip(I, J)):
+            h, s = hash_pair(seed, d, n, int(I_n), int(J_n))
+            hd.append(h)
+            sd.append(s)
+        hs.append(hd)
+        ss.append(sd)
+    return hs, ss
+
+
+def sketch_length(J) -> int:
+    """J~ = sum_n J_n - N + 1 (Definition 4)."""
+    return int(sum(int(j) for j in J) - len(J) + 1)
+
+
+# ---------------------------------------------------------------------------
+# Definition 1: count sketch, CS(x)_j = sum_{h(i) = j} s(i) x(i); applied
+# column by column when x is a matrix.
+# ---------------------------------------------------------------------------
+def count_sketch(x, h, s, J: int) -> np.ndarray:
+    x = np.asarray(x, dtype=np.float64)
+    out = np.zeros((J,) + x.shape[1:], dtype=np.float64)
+    np.add.at(out, np.asarray(h), np.asarray(s, dtype=np.float64).reshape(
+        (-1,) + (1,) * (x.ndim - 1)) * x)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Definition 4 / general-tensor formula of Section 3.2: FCS(T)_j is the sum of
+# S * T over all multi-indices whose bin H equals j.
+# ---------------------------------------------------------------------------
+def _bins_and_signs(h, s, shape):
+    """H and S over the full index grid, axes in mode order (mode 0 first)."""
+    N = len(shape)
+    H = np.zeros(shape, dtype=np.int64)
+    S = np.ones(shape, dtype=np.float64)
+    for n in range(N):
+        view = [1] * N
+        view[n] = shape[n]
+        H = H + np.asarray(h[n], dtype=np.int64).reshape(view)
+        S = S * np.asarray(s[n], dtype=np.float64).reshape(view)
+    return H, S
+
+
+def fcs_dense(T, h, s, J) -> np.ndarray:
+    """FCS of a dense tensor ``T`` (numpy array, axis n = mode n)."""
+    T = np.asarray(T, dtype=np.float64)
+    H, S = _bins_and_signs(h, s, T.shape)
+    return np.bincount(H.ravel(), weights=(S * T).ravel(),
+                       minlength=sketch_length(J)).astype(np.float64)
+
+
+def fcs_coo(idx, val, h, s, J) -> np.ndarray:
+    """FCS of a sparse tensor given as coordinates ``idx[n][k]`` and values
+    ``val[k]``; repeated coordinates add (the sketch is linear)."""
+    idx = [np.asarray(ix, dtype=np.int64) for ix in idx]
+    val = np.asarray(val, dtype=np.float64)
+    H = np.zeros(val.shape, dtype=np.int64)
+    S = np.ones(val.shape, dtype=np.float64)
+    for n, ix in enumerate(idx):
+        H += np.asarray(h[n], dtype=np.int64)[ix]
+        S *= np.asarray(s[n], dtype=np.float64)[ix]
+    return np.bincount(H, weights=S * val,
+                       minlength=sketch_length(J)).astype(np.float64)
+
+
+def vec(T) -> np.ndarray:
+    """vec(T) with mode 0 varying fastest (column-major), Section 2.1."""
+    return np.asarray(T).ravel(order="F")
+
+
+def unvec(v, shape) -> np.ndarray:
+    return np.asarray(v).reshape(shape, order="F")
+
+
+# ---------------------------------------------------------------------------
+# CP format: T = sum_r lambda_r u_r^(0) o ... o u_r^(N-1) (Section 2.1).
+# ---------------------------------------------------------------------------
+def cp_full(lam, U) -> np.ndarray:
+    """Materialise a CP tensor; ``U[n]`` is I_n x R."""
+    U = [np.asarray(u, dtype=np.float64) for u in U]
+    R = U[0].shape[1]
+    lam = np.ones(R) if lam is None else np.asarray(lam, dtype=np.float64)
+    shape = tuple(u.shape[0] for u in U)
+    T = np.zeros(shape, dtype=np.float64)
+    for r in range(R):
+        t = np.array(lam[r])
+        for u in U:
+            t = np.multiply.outer(t, u[:, r])
+        T += t
+    return T
+
+
+def fcs_cp_conv(lam, U, h, s, J) -> np.ndarray:
+    """FCS of a CP tensor as sum_r lambda_r CS_0(u_r) * ... * CS_{N-1}(u_r)
+    with * the full linear convolution (Section 3.1, second line of the CP
+    formula; exact by the polynomial-product identity proved there)."""
+    U = [np.asarray(u, dtype=np.float64) for u in U]
+    R = U[0].shape[1]
+    lam = np.ones(R) if lam is None else np.asarray(lam, dtype=np.float64)
+    Y = [count_sketch(U[n], h[n], s[n], int(J[n])) for n in range(len(U))]
+    out = np.zeros(sketch_length(J), dtype=np.float64)
+    for r in range(R):
+        y = Y[0][:, r]
+        for n in range(1, len(U)):
+            y = np.convolve(y, Y[n][:, r])
+        out += lam[r] * y
+    return out
+
+
+def fcs_cp_fft(lam, U, h, s, J, L: int | None = None) -> np.ndarray:
+    """Same sketch through zero-padded FFTs (Section 3.1, third line):
+    sum_r lambda_r F^-1( prod_n F(CS_n(U_n)(:, r), L) ), truncated to J~.
+    The paper pads to L = J~; any L >= J~ gives the same linear convolution."""
+    Jt = sketch_length(J)
+    L = Jt if L is None else int(L)
+    assert L >= Jt
+    U = [np.asarray(u, dtype=np.float64) for u in U]
+    R = U[0].shape[1]
+    lam = np.ones(R) if lam is None else np.asarray(lam, dtype=np.float64)
+    P = np.ones((L, R), dtype=np.complex128)
+    for n in range(len(U)):
+        P *= np.fft.fft(count_sketch(U[n], h[n], s[n], int(J[n])), n=L, axis=0)
+    spec = P @ lam
+    return np.fft.ifft(spec)[:Jt].real.copy()
+
+
+def fcs_spectrum(y, L: int) -> np.ndarray:
+    """F(y, L): the unnormalised L-point DFT of a zero-padded sketch."""
+    return np.fft.fft(np.asarray(y, dtype=np.float64), n=L)
+
+
+# ---------------------------------------------------------------------------
+# Definitions 2 and 3 (the comparison sketches), used only to pin the FCS
+# functions above through their stated relations.
+# ---------------------------------------------------------------------------
+def ts_dense(T, h, s, J: int) -> np.ndarray:
+    """Tensor sketch (Definition 2): bin (sum_n h_n(i_n)) mod J, all J_n = J."""
+    T = np.asarray(T, dtype=np.float64)
+    H, S = _bins_and_signs(h, s, T.shape)
+    return np.bincount((H % J).ravel(), weights=(S * T).ravel(),
+                       minlength=J).astype(np.float64)
+
+
+def hcs_dense(T, h, s, J) -> np.ndarray:
+    """Higher-order count sketch (Definition 3): a J_0 x ... x J_{N-1} tensor."""
+    T = np.asarray(T, dtype=np.float64)
+    out = np.zeros(tuple(int(j) for j in J), dtype=np.float64)
+    N = T.ndim
+    grids = np.meshgrid(*[np.arange(n_) for n_ in T.shape], indexing="ij")
+    S = np.ones(T.shape)
+    idx = []
+    for n in range(N):
+        idx.append(np.asarray(h[n])[grids[n]])
+        S = S * np.asarray(s[n], dtype=np.float64)[grids[n]]
+    np.add.at(out, tuple(idx), S * T)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Sketched contractions (Section 3.3 and Section 4): inner products of D
+# independent sketches reduced by the median.
+# ---------------------------------------------------------------------------
+def inner(a, b) -> np.ndarray:
+    """<a_d, b_d> for each sketch d (rows of a and b)."""
+    a = np.atleast_2d(np.asarray(a, dtype=np.float64))
+    b = np.atleast_2d(np.asarray(b, dtype=np.float64))
+    return np.sum(a * b, axis=1)
+
+
+def median(x, axis=0):
+    """Median over the D independent sketches (numpy convention: the mean of
+    the two middle order statistics when D is even)."""
+    return np.median(np.asarray(x, dtype=np.float64), axis=axis)
+
+
+def inner_median(a, b):
+    per_d = inner(a, b)
+    return median(per_d), per_d
+
+
+def contract_free(y, h, s, J, free: int, vecs) -> np.ndarray:
+    """Estimate of T(..., I, ...) with the identity at mode ``free`` and the
+    given vectors at every other mode, from one sketch y = FCS(T).
+
+    By Section 4.1 the i-th entry is <FCS(T), FCS(e_i o v ...)>.  The sketch of
+    that rank-1 tensor is s_f(i) times g shifted by h_f(i), where g is the
+    linear convolution of CS_n(v_n) over the modes n != f (Section 3.1), so
+    the inner product is s_f(i) * sum_m y[h_f(i) + m] g[m]."""
+    y = np.asarray(y, dtype=np.float64)
+    N = len(J)
+    others = [n for n in range(N) if n != free]
+    g = np.ones(1)
+    for k, n in enumerate(others):
+        g = np.convolve(g, count_sketch(vecs[k], h[n], s[n], int(J[n])))
+    corr = np.correlate(y, g, mode="valid")          # length J_free
+    assert corr.shape[0] == int(J[free])
+    hf = np.asarray(h[free], dtype=np.int64)
+    sf = np.asarray(s[free], dtype=np.float64)
+    return sf * corr[hf]
+
+
+def contract_free_fft(y, h, s, J, L: int, vecs) -> np.ndarray:
+    """The FFT form of the same estimate for an order-3 tensor with the free
+    index at mode 0 (Section 4.1): z = F^-1(F(y) conj(F(CS_1 u)) conj(F(CS_2 v))),
+    entry i = s_0(i) z(h_0(i)); F is the L-point DFT, L >= J~."""
+    u, v = vecs
+    Fy = np.fft.fft(np.asarray(y, dtype=np.float64), n=L)
+    F1 = np.fft.fft(count_sketch(u, h[1], s[1], int(J[1])), n=L)
+    F2 = np.fft.fft(count_sketch(v, h[2], s[2], int(J[2])), n=L)
+    z = np.fft.ifft(Fy * np.conj(F1) * np.conj(F2)).real
+    return np.asarray(s[0], dtype=np.float64) * z[np.asarray(h[0])]
+
+
+def contract_free_median(Y, hs, ss, J, free, vecs) -> np.ndarray:
+    """Median over the D sketches (rows of Y, each with its own hash pairs)."""
+    est = np.stack([contract_free(Y[d], hs[d], ss[d], J, free, vecs)
+                    for d in range(len(Y))])
+    return median(est, axis=0)
+
+
+def contract_full(y, h, s, J, vecs) -> float:
+    """T(v_0, ..., v_{N-1}) estimate <FCS(T), FCS(v_0 o ... o v_{N-1})>
+    (Section 4.1)."""
+    g = np.ones(1)
+    for n, v in enumerate(vecs):
+        g = np.convolve(g, count_sketch(v, h[n], s[n], int(J[n])))
+    return float(np.dot(np.asarray(y, dtype=np.float64), g))
+
+
+# ---------------------------------------------------------------------------
+# Kronecker-product compression (Section 4.3): the order-4 tensor
+# T[i1, i2, i3, i4] = A[i1, i2] B[i3, i4] has
+# FCS(A (x) B) = F^-1( F(FCS_{1,2}(A), J~) * F(FCS_{3,4}(B), J~) ).
+# ---------------------------------------------------------------------------
+def kron_fcs(A, B, h, s, J) -> np.ndarray:
+    a = fcs_dense(A, h[0:2], s[0:2], J[0:2])
+    b = fcs_dense(B, h[2:4], s[2:4], J[2:4])
+    Jt = sketch_length(J)
+    return np.fft.ifft(np.fft.fft(a, n=Jt) * np.fft.fft(b, n=Jt)).real.copy()
+
+
+def kron_decompress(y, h, s, I) -> np.ndarray:
+    """Entry (i1,i2,i3,i4) of the recovered order-4 tensor is
+    s1 s2 s3 s4 * FCS[h1 + h2 + h3 + h4] (Section 4.3; 0-based, so the
+    paper's modulo never wraps)."""
+    H, S = _bins_and_signs(h, s, tuple(int(i) for i in I))
+    return S * np.asarray(y, dtype=np.float64)[H]

@@ -1,0 +1,186 @@
+"""Seeded synthetic inputs for fast count sketch workloads.
+
+This module only draws random numbers and shapes; it holds none of the
+sketch's arithmetic (no hashing, no sketching).  It is the one module that
+both the oracle-side tests and the GPU-side tests and bench read inputs from,
+so that both sides see identical float32 values.
+
+Every generator is ``numpy.random.Generator(PCG64(seed))``.  Workloads follow
+the synthetic set-ups of the paper (Gaussian CP factors, Gaussian dense
+tensors, uniform [-5, 5] Kronecker factors, Section 4) at the sizes of the
+five benchmark configurations:
+
+* ``cp100``      order 3, I_n = 100, R = 10, J_n = 64 (J~ = 190), D = 5
+* ``dense1024``  order 3, 1024^3 float32 N(0,1), J_n = 4096 (J~ = 12286), D = 8,
+                 plus a 10 % Bernoulli-masked COO copy with int32 coordinates
+* ``cp10k``      order 3, I_n = 10^4, R = 512, unit-norm N(0,1) columns,
+                 J_n = 2^14, D = 10, 64 unit vector pairs for T(I, u, v)
+* ``batch4096``  4096 uneven CP instances (N in {3,4,5}, I_n log-uniform in
+                 [32, 4096], R in [1, 256], J_n = 2^{8..13}), every 16th a
+                 Kronecker instance of two 256 x 256 U[-5, 5] matrices
+* ``serve``      Poisson request streams over the shapes above
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+DATA_SEED = {"cp100": 1001, "dense1024": 1002, "cp10k": 1003, "batch4096": 1004,
+             "serve": 1005}
+HASH_SEED = {"cp100": 2001, "dense1024": 2002, "cp10k": 2003, "batch4096": 2004,
+             "serve": 2005}
+
+
+def rng(seed: int, *stream: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64([seed, *stream] if stream else seed))
+
+
+# ----------------------------------------------------------------------------
+# primitive draws
+# ----------------------------------------------------------------------------
+def cp_factors(seed: int, I, R: int, normalize: bool = False, stream: int = 0):
+    """N factor matrices U_n (I_n x R), float64 N(0,1) draws cast to float32;
+    with ``normalize`` every column is scaled to unit 2-norm first."""
+    g = rng(seed, stream)
+    out = []
+    for I_n in I:
+        u = g.standard_normal((int(I_n), int(R)))
+        if normalize:
+            u = u / np.linalg.norm(u, axis=0, keepdims=True)
+        out.append(u.astype(np.float32))
+    return out
+
+
+def dense_tensor(seed: int, I, stream: int = 0) -> np.ndarray:
+    """vec(T) (mode 0 fastest) of a float32 N(0,1) tensor, drawn directly in
+    float32."""
+    n = int(np.prod([int(i) for i in I]))
+    return rng(seed, stream).standard_normal(n, dtype=np.float32)
+
+
+def integer_tensor(seed: int, I, lo: int = -3, hi: int = 3, stream: int = 0):
+    """Small-integer tensor (float32) whose every partial sum is exact."""
+    n = int(np.prod([int(i) for i in I]))
+    return rng(seed, stream).integers(lo, hi + 1, size=n).astype(np.float32)
+
+
+def bernoulli_coo(seed: int, T_vec: np.ndarray, I, density: float,
+                  chunk: int = 1 << 26, stream: int = 1):
+    """Keep each linear index with probability ``density`` (seeded); returns
+    (idx int32 [N][nnz] mode-major, val float32 [nnz]) sorted by linear index."""
+    g = rng(seed, stream)
+    I = [int(i) for i in I]
+    total = T_vec.size
+    keep = []
+    for start in range(0, total, chunk):
+        m = g.random(min(chunk, total - start), dtype=np.float32) < density
+        keep.append(np.flatnonzero(m).astype(np.int64) + start)
+    lin = np.concatenate(keep) if keep else np.zeros(0, np.int64)
+    val = T_vec[lin].astype(np.float32)
+    idx = np.empty((len(I), lin.size), dtype=np.int32)
+    rem = lin
+    for n, I_n in enumerate(I):
+        idx[n] = (rem % I_n).astype(np.int32)
+        rem = rem // I_n
+    return idx, val
+
+
+def unit_vectors(seed: int, count: int, size: int, stream: int = 0) -> np.ndarray:
+    """``count`` x ``size`` float32 rows, N(0,1) draws scaled to unit norm."""
+    v = rng(seed, stream).standard_normal((count, size))
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    return v.astype(np.float32)
+
+
+def uniform_matrix(seed: int, shape, lo=-5.0, hi=5.0, stream: int = 0):
+    return rng(seed, stream).uniform(lo, hi, size=shape).astype(np.float32)
+
+
+# ----------------------------------------------------------------------------
+# benchmark configurations
+# ----------------------------------------------------------------------------
+@dataclass
+class CPConfig:
+    name: str
+    I: tuple
+    J: tuple
+    R: int
+    D: int
+    normalize: bool
+    data_seed: int
+    hash_seed: int
+    pairs: int = 0
+
+    def factors(self, stream: int = 0):
+        return cp_factors(self.data_seed, self.I, self.R, self.normalize, stream)
+
+
+CP100 = CPConfig("cp100", (100, 100, 100), (64, 64, 64), 10, 5, False,
+                 DATA_SEED["cp100"], HASH_SEED["cp100"])
+CP10K = CPConfig("cp10k", (10000, 10000, 10000), (16384, 16384, 16384), 512, 10,
+                 True, DATA_SEED["cp10k"], HASH_SEED["cp10k"], pairs=64)
+
+
+@dataclass
+class DenseConfig:
+    name: str
+    I: tuple
+    J: tuple
+    D: int
+    data_seed: int
+    hash_seed: int
+    density: float = 0.1
+
+
+DENSE1024 = DenseConfig("dense1024", (1024, 1024, 1024), (4096, 4096, 4096), 8,
+                        DATA_SEED["dense1024"], HASH_SEED["dense1024"])
+
+
+@dataclass
+class Instance:
+    """One CP (or Kronecker) sketch request of the uneven batch."""
+    index: int
+    kind: str            # "cp" or "kron"
+    I: tuple
+    J: tuple
+    R: int
+    D: int = 1
+    seed: int = 0        # data seed of this instance
+    hash_seed: int = 0
+    extra: dict = field(default_factory=dict)
+
+    def factors(self):
+        if self.kind == "kron":
+            A = uniform_matrix(self.seed, (self.I[0], self.I[1]), stream=1)
+            B = uniform_matrix(self.seed, (self.I[2], self.I[3]), stream=2)
+            return [A, B]
+        return cp_factors(self.seed, self.I, self.R, False, stream=0)
+
+
+def batch_instances(count: int = 4096, seed: int = DATA_SEED["batch4096"],
+                    hash_seed: int = HASH_SEED["batch4096"], kron_every: int = 16,
+                    I_range=(32, 4096), R_range=(1, 256), logJ_range=(8, 13)):
+    """The uneven batch: instance k draws its shape from stream (seed, k)."""
+    out = []
+    lo, hi = np.log(I_range[0]), np.log(I_range[1])
+    for k in range(count):
+        g = rng(seed, 7, k)
+        if kron_every and k % kron_every == kron_every - 1:
+            Jk = int(2 ** g.integers(logJ_range[0], logJ_range[1] + 1))
+            out.append(Instance(k, "kron", (256, 256, 256, 256), (Jk,) * 4, 1,
+                                seed=seed * 1000003 + k, hash_seed=hash_seed + k))
+            continue
+        N = int(g.integers(3, 6))
+        I = tuple(int(np.exp(g.uniform(lo, hi))) for _ in range(N))
+        R = int(g.integers(R_range[0], R_range[1] + 1))
+        J = tuple(int(2 ** g.integers(logJ_range[0], logJ_range[1] + 1))
+                  for _ in range(N))
+        out.append(Instance(k, "cp", I, J, R, seed=seed * 1000003 + k,
+                            hash_seed=hash_seed + k))
+    return out
+
+
+def poisson_arrivals(seed: int, rate: float, count: int) -> np.ndarray:
+    """Arrival times (s) of a Poisson stream: cumulative exponential gaps."""
+    return np.cumsum(rng(seed, 11).exponential(1.0 / rate, size=count))
