@@ -1,0 +1,238 @@
+/*
+ * fcs.h -- C ABI of the MI355X (gfx950) fast count sketch library, libfcs.so.
+ *
+ * The operations follow Cao and Liu, "Efficient Tensor Contraction via Fast
+ * Count Sketch" (arXiv 2106.13062):
+ *   - Definition 4 and the general-tensor formula of Section 3.2: the FCS of
+ *     a tensor T of order N is the count sketch of vec(T) under the implicit
+ *     long hash pair H = sum_n h_n(i_n), S = prod_n s_n(i_n); it has
+ *     J~ = sum_n J_n - N + 1 entries.
+ *   - Section 3.1: for a CP tensor [[lambda; U_0..U_{N-1}]] the same sketch is
+ *     sum_r lambda_r F^-1(prod_n F(CS_n(U_n)(:, r))) with zero-padded FFTs.
+ *   - Section 3.3 (Proposition 1) and Section 4: sketched contractions are
+ *     inner products of sketches made with the same hash functions, and the
+ *     estimate is the median over D independent sketches; T(I, u, v) uses the
+ *     FFT form of Section 4.1.
+ *
+ * Conventions for every entry point
+ *   - Indices are 0-based: h_n(i) is in [0, J_n), bins are in [0, J~).
+ *   - Dense tensors are vec(T): mode 0 varies fastest (the paper's
+ *     column-major vec); a C-contiguous array of shape (I_{N-1}, ..., I_0)
+ *     is exactly that.
+ *   - Device pointers are HIP device addresses of the current device; host
+ *     pointers are ordinary process memory.  Every pointer argument says
+ *     which it is.
+ *   - The library never allocates or frees device memory.  Hash tables and
+ *     workspaces are caller-owned device buffers whose sizes the library
+ *     reports (fcs_plan_table_bytes, fcs_workspace_bytes).  Plans are small
+ *     host objects owned by the caller until fcs_plan_destroy.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls are asynchronous on that stream unless stated otherwise; the
+ *     library keeps no pointer beyond the work it enqueued.
+ *   - Every argument is validated before anything is enqueued; on any error
+ *     the call returns a non-zero fcs_status, enqueues nothing and leaves
+ *     every output untouched.  fcs_last_error() then describes the problem.
+ *     A failed kernel launch returns FCS_EDEVICE.  No exception crosses the
+ *     ABI.
+ *   - A bound plan is read-only and may be used from several streams at
+ *     once; concurrent calls need separate workspaces.
+ *   - Both operands of any sketched contraction must come from the same plan
+ *     (same seed, shapes and hash lengths): Proposition 1 compares sketches
+ *     made with identical hash functions.
+ */
+#ifndef FCS_H
+#define FCS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* exported symbols of libfcs.so (the library is built with hidden default
+ * visibility) */
+#if defined(__GNUC__) || defined(__clang__)
+#define FCS_API __attribute__((visibility("default")))
+#else
+#define FCS_API
+#endif
+
+#define FCS_MAX_ORDER 8      /* largest supported order N                  */
+#define FCS_MAX_D 64         /* largest number of independent sketches D   */
+#define FCS_MAX_FFT 16384    /* largest LDS-resident FFT size P            */
+
+typedef enum {
+    FCS_OK = 0,
+    FCS_EINVAL = 1,          /* bad argument (shape, pointer, size, mode)   */
+    FCS_ENOMEM = 2,          /* caller buffer smaller than required         */
+    FCS_EADMIT = 3,          /* batch rejected by the admission bound       */
+    FCS_EDEVICE = 4,         /* a HIP call or kernel launch failed          */
+    FCS_EUNSUPPORTED = 5     /* valid request outside this build's limits   */
+} fcs_status;
+
+typedef struct fcs_plan *fcs_plan_t;
+
+/* Plan description (Definition 4): order N, mode sizes I_n, hash lengths
+ * J_n, D independent sketches and the seed of all hash pairs.
+ *   N      1..FCS_MAX_ORDER
+ *   I      host array of N sizes, each >= 1, product < 2^62
+ *   J      host array of N hash lengths, each >= 1, J~ < 2^31
+ *   D      1..FCS_MAX_D
+ *   seed   64-bit seed of the hash family (see fcs_plan_bind)
+ *   L      transform length of the CP / spectral paths; 0 lets the plan
+ *          choose.  A caller value must be >= J~ and of the form Q * P with
+ *          P a power of two in [256, FCS_MAX_FFT] and 1 <= Q <= 64.  The
+ *          paper pads to J~ points (Section 3.1); any L >= J~ gives the same
+ *          linear convolution, so L only changes rounding. */
+typedef struct {
+    int32_t N;
+    const int64_t *I;
+    const int64_t *J;
+    int32_t D;
+    uint64_t seed;
+    int64_t L;
+} fcs_plan_desc;
+
+/* Validate a description and build a host plan (no device work).
+ * out: host pointer receiving the plan.  Errors: FCS_EINVAL, FCS_EUNSUPPORTED. */
+FCS_API fcs_status fcs_plan_create(const fcs_plan_desc *desc, fcs_plan_t *out);
+
+/* Bytes of device memory fcs_plan_bind needs for hash and twiddle tables. */
+FCS_API size_t fcs_plan_table_bytes(fcs_plan_t plan);
+
+/* Fill the plan's tables into caller device memory `dev_tables` (at least
+ * fcs_plan_table_bytes bytes, 256-byte aligned) on `stream`, and attach that
+ * memory to the plan.  The buffer must stay allocated and unmodified while
+ * the plan is used.  Hash pairs: for sketch d and mode n,
+ *   key = mix(mix(seed) + d * 2^16 + n),  y = mix(key + i),
+ *   h_n(i) = ((y >> 32) * J_n) >> 32,     s_n(i) = (y & 1) ? -1 : +1,
+ * where mix is the SplitMix64 output function (Steele, Lea, Flood 2014);
+ * the paper asks only for 2-wise independent pairs (Definitions 1-4).
+ * Twiddles are evaluated in double precision and stored as float.
+ * Errors: FCS_EINVAL (null or misaligned buffer), FCS_EDEVICE. */
+FCS_API fcs_status fcs_plan_bind(fcs_plan_t plan, void *dev_tables, void *stream);
+
+/* Copy hash pair (h_n, s_n) of sketch d from the bound device tables to host
+ * arrays h_host[I_n] and s_host[I_n].  Synchronises `stream`.
+ * Errors: FCS_EINVAL (unbound plan, d or n out of range), FCS_EDEVICE. */
+FCS_API fcs_status fcs_plan_export(fcs_plan_t plan, int32_t d, int32_t n,
+                           int32_t *h_host, int8_t *s_host, void *stream);
+
+/* Sizes of the plan: J~ (sketch length), L = Q * P (transform length), P
+ * (FFT size) and Q (number of length-P slices of the transform).  Any output
+ * pointer may be NULL. */
+FCS_API fcs_status fcs_plan_info(fcs_plan_t plan, int64_t *Jtilde, int64_t *L,
+                         int64_t *P, int32_t *Q);
+
+/* Number of spectrum entries (complex) per sketch in the `spec` layout used
+ * by fcs_sketch_cp, fcs_sketch_spectrum and fcs_contract_free_mode:
+ * (floor(Q/2) + 1) * P.  spec[d][q][k] = X_d[Q*k + q], X_d the L-point DFT
+ * (unnormalised, e^{-2 pi i jk/L}) of sketch d zero-padded to L, for
+ * q = 0..floor(Q/2), k = 0..P-1; the other frequencies follow from X_d being
+ * the transform of a real sequence. */
+FCS_API int64_t fcs_plan_spec_len(fcs_plan_t plan);
+
+/* Release a plan (host memory only; the caller still owns dev_tables). */
+FCS_API fcs_status fcs_plan_destroy(fcs_plan_t plan);
+
+/* Workspace operations. */
+enum {
+    FCS_OP_DENSE = 0,        /* fcs_sketch_dense                            */
+    FCS_OP_COO = 1,          /* fcs_sketch_coo                              */
+    FCS_OP_CP = 2,           /* fcs_sketch_cp with rank R                   */
+    FCS_OP_INNER = 3,        /* fcs_contract_inner                          */
+    FCS_OP_FREE_MODE = 4,    /* fcs_contract_free_mode with P pairs         */
+    FCS_OP_SPECTRUM = 5      /* fcs_sketch_spectrum                         */
+};
+
+/* Device workspace bytes an operation needs (R: CP rank, P: vector pairs;
+ * ignored where irrelevant).  Returns 0 for an invalid operation. */
+FCS_API size_t fcs_workspace_bytes(fcs_plan_t plan, int32_t op, int64_t R, int64_t P);
+
+/* Dense sketch, general-tensor formula of Section 3.2, all D sketches in one
+ * pass over T.
+ *   T    device, float, prod_n I_n entries in vec order (mode 0 fastest)
+ *   out  device, float, D x J~ row-major; overwritten
+ *   ws   device workspace of ws_bytes >= fcs_workspace_bytes(FCS_OP_DENSE)
+ * Float sums are accumulated in a scheduling-dependent order, so results may
+ * differ between runs by rounding; integer-valued inputs whose partial sums
+ * stay below 2^24 are exact.  Errors: FCS_EINVAL, FCS_ENOMEM, FCS_EDEVICE. */
+FCS_API fcs_status fcs_sketch_dense(fcs_plan_t plan, const float *T, float *out,
+                            void *ws, size_t ws_bytes, void *stream);
+
+/* COO sketch: the same formula over nnz coordinates; repeated coordinates
+ * add (the sketch is linear).
+ *   idx  device, int32, N x nnz mode-major (idx[n*nnz + k] = i_n of entry k),
+ *        each in [0, I_n)
+ *   val  device, float, nnz values
+ *   out  device, float, D x J~; overwritten
+ * nnz = 0 gives a zero sketch.  Indices are trusted: out-of-range indices
+ * are undefined behaviour (validate on the host if they are untrusted).
+ * Errors: FCS_EINVAL, FCS_ENOMEM, FCS_EDEVICE. */
+FCS_API fcs_status fcs_sketch_coo(fcs_plan_t plan, int64_t nnz, const int32_t *idx,
+                          const float *val, float *out, void *ws,
+                          size_t ws_bytes, void *stream);
+
+/* CP sketch, Section 3.1: per-mode count sketch of every factor column,
+ * zero-padded L-point FFT, mode-wise product, sum over the R ranks weighted
+ * by lambda, inverse FFT, truncation to J~.
+ *   R       rank >= 0 (R = 0 gives a zero sketch)
+ *   U       host array of N device pointers; U[n] is the I_n x R factor
+ *           stored column-major (column r is U[n][r*I_n .. r*I_n + I_n))
+ *   lambda  device, float, R weights, or NULL for all ones
+ *   out     device, float, D x J~; overwritten (may be NULL if spec is set)
+ *   spec    device, float2 (re, im), D x fcs_plan_spec_len, or NULL; receives
+ *           the spectrum of each sketch in the layout of fcs_plan_spec_len
+ * Errors: FCS_EINVAL, FCS_ENOMEM, FCS_EUNSUPPORTED, FCS_EDEVICE. */
+FCS_API fcs_status fcs_sketch_cp(fcs_plan_t plan, int64_t R, const float *const *U,
+                         const float *lambda, float *out, float *spec,
+                         void *ws, size_t ws_bytes, void *stream);
+
+/* Spectrum of existing sketches (for contractions of dense or COO sketches):
+ *   y     device, float, D x J~
+ *   spec  device, float2, D x fcs_plan_spec_len; overwritten
+ * Errors: FCS_EINVAL, FCS_ENOMEM, FCS_EUNSUPPORTED, FCS_EDEVICE. */
+FCS_API fcs_status fcs_sketch_spectrum(fcs_plan_t plan, const float *y, float *spec,
+                               void *ws, size_t ws_bytes, void *stream);
+
+/* Sketched inner product, Proposition 1 and Section 4: per sketch d,
+ * ip_d = sum_j a[d][j] b[d][j] (float inputs, products and sums in double),
+ * and the median over d (mean of the two middle values for even D).
+ *   a, b    device, float, D x J~ (sketches from the same plan)
+ *   median  device, double, 1 value
+ *   per_d   device, double, D values, or NULL
+ * Errors: FCS_EINVAL, FCS_ENOMEM, FCS_EDEVICE. */
+FCS_API fcs_status fcs_contract_inner(fcs_plan_t plan, const float *a, const float *b,
+                              double *median, double *per_d, void *ws,
+                              size_t ws_bytes, void *stream);
+
+/* T(I, u, v)-type contraction, Section 4.1: the identity at mode
+ * `free_mode` and a vector at every other mode.  For each sketch d and pair
+ * p, z = F^-1(X_d prod_{n != free} conj(F(CS_n(v_{n,p})))) and
+ * est_{d,p}(i) = s_free(i) z(h_free(i)); out[p][i] = median over d.
+ *   spec       device, float2, D x fcs_plan_spec_len (from fcs_sketch_cp or
+ *              fcs_sketch_spectrum of the sketched tensor)
+ *   free_mode  0..N-1
+ *   P          number of vector tuples >= 0
+ *   vecs       host array of N device pointers; vecs[free_mode] is ignored
+ *              (may be NULL), vecs[n] is P x I_n row-major float
+ *   out        device, double, P x I_free row-major
+ * Errors: FCS_EINVAL, FCS_ENOMEM, FCS_EUNSUPPORTED, FCS_EDEVICE. */
+FCS_API fcs_status fcs_contract_free_mode(fcs_plan_t plan, const float *spec,
+                                  int32_t free_mode, int64_t P,
+                                  const float *const *vecs, double *out,
+                                  void *ws, size_t ws_bytes, void *stream);
+
+/* Text of a status code (static storage). */
+FCS_API const char *fcs_status_str(fcs_status status);
+
+/* Description of the last error raised on the calling thread (static or
+ * thread-local storage; empty when the last call succeeded). */
+FCS_API const char *fcs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FCS_H */

@@ -1,0 +1,78 @@
+// Internal declarations shared by the translation units of libfcs.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "fcs.h"
+
+// Packed hash word of sketch d, mode n, index i: bits 0..30 hold h_n(i),
+// bit 31 is set when s_n(i) = -1.  Storing the sign as the float sign bit
+// lets kernels apply it with one XOR.
+constexpr uint32_t FCS_H_MASK = 0x7fffffffu;
+constexpr uint32_t FCS_S_BIT = 0x80000000u;
+
+constexpr int FCS_MIN_FFT = 256;
+constexpr size_t FCS_LDS_BYTES = 160 * 1024;   // LDS per CU on gfx950
+
+struct fcs_plan {
+    int N = 0, D = 0;
+    int64_t I[FCS_MAX_ORDER] = {0}, J[FCS_MAX_ORDER] = {0};
+    int64_t off[FCS_MAX_ORDER] = {0};   // offset of mode n inside a sketch's table
+    int64_t sumI = 0;
+    uint64_t seed = 0;
+    int64_t Jt = 0;                    // J~ = sum J_n - N + 1
+    int64_t L = 0, P = 0;              // transform length L = Q * P, FFT size P
+    int Q = 0, Qh = 0;                 // slices, stored slices floor(Q/2)+1
+    // device layout inside the caller's table buffer
+    size_t tab_off = 0, twP_off = 0, twL_off = 0, total = 0;
+    const uint32_t *tab = nullptr;     // D x sumI packed hash words
+    const float2 *twP = nullptr;       // exp(-2 pi i k / P), k < P
+    const float2 *twL = nullptr;       // exp(-2 pi i k / L), k < L
+    bool bound = false;
+};
+
+// error reporting ----------------------------------------------------------
+void fcs_set_error(const char *fmt, ...);
+void fcs_clear_error();
+
+#define FCS_FAIL(code, ...)              \
+    do {                                 \
+        fcs_set_error(__VA_ARGS__);      \
+        return (code);                   \
+    } while (0)
+
+#define FCS_HIP_CHECK(expr)                                                   \
+    do {                                                                      \
+        hipError_t e_ = (expr);                                               \
+        if (e_ != hipSuccess)                                                 \
+            FCS_FAIL(FCS_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+#define FCS_LAUNCH_CHECK()                                                     \
+    do {                                                                       \
+        hipError_t e_ = hipGetLastError();                                     \
+        if (e_ != hipSuccess)                                                  \
+            FCS_FAIL(FCS_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e_)); \
+    } while (0)
+
+static inline bool fcs_aligned(const void *p, size_t a) {
+    return (reinterpret_cast<uintptr_t>(p) % a) == 0;
+}
+
+static inline int64_t fcs_ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// shared launch helpers (defined in plan.hip) --------------------------------
+fcs_status fcs_zero_fill(float *p, int64_t n, hipStream_t s);
+int fcs_device_cu_count();
+
+// workspace sizes of each operation (defined next to the kernels)
+size_t fcs_ws_dense(const fcs_plan *p);
+size_t fcs_ws_coo(const fcs_plan *p);
+size_t fcs_ws_cp(const fcs_plan *p, int64_t R);
+size_t fcs_ws_inner(const fcs_plan *p);
+size_t fcs_ws_free_mode(const fcs_plan *p, int64_t P);
+size_t fcs_ws_spectrum(const fcs_plan *p);

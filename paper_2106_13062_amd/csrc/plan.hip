@@ -1,0 +1,306 @@
+// Plans: validation, sizes, seeded hash tables and twiddle tables on the
+// device, status strings and small shared launch helpers.
+#include "fcs_internal.h"
+
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+#include <new>
+
+// ---------------------------------------------------------------------------
+// error state (per host thread)
+// ---------------------------------------------------------------------------
+static thread_local char g_err[512];
+
+void fcs_set_error(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+void fcs_clear_error() { g_err[0] = '\0'; }
+
+extern "C" const char *fcs_last_error(void) { return g_err; }
+
+extern "C" const char *fcs_status_str(fcs_status s) {
+    switch (s) {
+    case FCS_OK: return "FCS_OK";
+    case FCS_EINVAL: return "FCS_EINVAL: invalid argument";
+    case FCS_ENOMEM: return "FCS_ENOMEM: caller buffer too small";
+    case FCS_EADMIT: return "FCS_EADMIT: rejected by the admission bound";
+    case FCS_EDEVICE: return "FCS_EDEVICE: HIP call or kernel launch failed";
+    case FCS_EUNSUPPORTED: return "FCS_EUNSUPPORTED: outside this build's limits";
+    }
+    return "unknown fcs_status";
+}
+
+int fcs_device_cu_count() {
+    int dev = 0, cu = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
+            cu = prop.multiProcessorCount;
+    }
+    return cu;
+}
+
+// ---------------------------------------------------------------------------
+// device hash family: SplitMix64 output function (Steele, Lea, Flood 2014)
+// ---------------------------------------------------------------------------
+__host__ __device__ static inline uint64_t sm64_mix(uint64_t x) {
+    uint64_t z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+struct HashArgs {
+    uint32_t *tab;
+    uint64_t seed_mixed;   // mix(seed)
+    int64_t off[FCS_MAX_ORDER + 1];
+    int64_t J[FCS_MAX_ORDER];
+    int N;
+    int64_t sumI;
+    int64_t total;         // D * sumI
+};
+
+__global__ void hash_tables_kernel(HashArgs a) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= a.total) return;
+    const int64_t d = t / a.sumI;
+    const int64_t e = t - d * a.sumI;
+    int n = 0;
+    while (n + 1 < a.N && e >= a.off[n + 1]) ++n;
+    const int64_t i = e - a.off[n];
+    const uint64_t key = sm64_mix(a.seed_mixed + ((uint64_t)d << 16) + (uint64_t)n);
+    const uint64_t y = sm64_mix(key + (uint64_t)i);
+    const uint64_t h = ((y >> 32) * (uint64_t)a.J[n]) >> 32;
+    a.tab[t] = (uint32_t)h | ((y & 1ull) ? FCS_S_BIT : 0u);
+}
+
+// exp(-2 pi i k / n) evaluated in double precision, stored as float.
+__global__ void twiddle_kernel(float2 *w, int64_t n) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    double s, c;
+    sincospi(-2.0 * (double)k / (double)n, &s, &c);
+    w[k] = make_float2((float)c, (float)s);
+}
+
+__global__ void zero_fill_kernel(float4 *p4, int64_t n4, float *tail, int64_t ntail) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n4; k += stride)
+        p4[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < ntail) tail[k] = 0.f;
+}
+
+fcs_status fcs_zero_fill(float *p, int64_t n, hipStream_t s) {
+    if (n <= 0) return FCS_OK;
+    // align the vector part to 16 bytes
+    int64_t head = 0;
+    while (head < n && !fcs_aligned(p + head, 16)) ++head;
+    if (head > 0) {
+        zero_fill_kernel<<<1, 64, 0, s>>>(nullptr, 0, p, head);
+        FCS_LAUNCH_CHECK();
+    }
+    const int64_t n4 = (n - head) / 4;
+    const int64_t ntail = (n - head) - n4 * 4;
+    int64_t blocks = std::min<int64_t>(fcs_ceil_div(std::max<int64_t>(n4, 1), 256), 4096);
+    zero_fill_kernel<<<(unsigned)blocks, 256, 0, s>>>(reinterpret_cast<float4 *>(p + head), n4,
+                                                     p + head + n4 * 4, ntail);
+    FCS_LAUNCH_CHECK();
+    return FCS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// transform length: L = Q * P, P a power of two in [FCS_MIN_FFT, FCS_MAX_FFT]
+// ---------------------------------------------------------------------------
+static double cp_cost(const fcs_plan *p, int64_t P, int Q) {
+    // per (sketch, rank): for each stored slice and mode, a scatter of I_n
+    // factor entries and one P-point FFT (cost model, arbitrary units)
+    const int Qh = Q / 2 + 1;
+    double lg = std::log2((double)P);
+    double per_mode = 0.0;
+    for (int n = 0; n < p->N; ++n) per_mode += 3.0 * (double)p->I[n] + (double)P * lg;
+    return (double)Qh * per_mode;
+}
+
+static bool choose_transform(fcs_plan *p, int64_t Lreq) {
+    if (Lreq > 0) {
+        for (int64_t P = FCS_MAX_FFT; P >= FCS_MIN_FFT; P /= 2) {
+            if (Lreq % P) continue;
+            int64_t Q = Lreq / P;
+            if (Q >= 1 && Q <= 64) {
+                p->P = P;
+                p->Q = (int)Q;
+                p->L = Lreq;
+                return true;
+            }
+        }
+        return false;
+    }
+    double best = 0.0;
+    bool found = false;
+    for (int64_t P = FCS_MIN_FFT; P <= FCS_MAX_FFT; P *= 2) {
+        int64_t Q = fcs_ceil_div(p->Jt, P);
+        if (Q > 64) continue;
+        double c = cp_cost(p, P, (int)Q);
+        if (!found || c < best) {
+            best = c;
+            found = true;
+            p->P = P;
+            p->Q = (int)Q;
+            p->L = P * Q;
+        }
+    }
+    return found;
+}
+
+extern "C" fcs_status fcs_plan_create(const fcs_plan_desc *desc, fcs_plan_t *out) {
+    fcs_clear_error();
+    if (!desc || !out) FCS_FAIL(FCS_EINVAL, "null description or output pointer");
+    if (desc->N < 1 || desc->N > FCS_MAX_ORDER)
+        FCS_FAIL(FCS_EINVAL, "order N=%d outside [1, %d]", desc->N, FCS_MAX_ORDER);
+    if (!desc->I || !desc->J) FCS_FAIL(FCS_EINVAL, "null I or J array");
+    if (desc->D < 1 || desc->D > FCS_MAX_D)
+        FCS_FAIL(FCS_EINVAL, "D=%d outside [1, %d]", desc->D, FCS_MAX_D);
+    fcs_plan tmp;
+    tmp.N = desc->N;
+    tmp.D = desc->D;
+    tmp.seed = desc->seed;
+    double prodI = 1.0;
+    int64_t sumJ = 0;
+    for (int n = 0; n < tmp.N; ++n) {
+        if (desc->I[n] < 1) FCS_FAIL(FCS_EINVAL, "I[%d]=%lld < 1", n, (long long)desc->I[n]);
+        if (desc->J[n] < 1) FCS_FAIL(FCS_EINVAL, "J[%d]=%lld < 1", n, (long long)desc->J[n]);
+        if (desc->I[n] > INT32_MAX) FCS_FAIL(FCS_EUNSUPPORTED, "I[%d] exceeds 2^31-1", n);
+        if (desc->J[n] > INT32_MAX) FCS_FAIL(FCS_EUNSUPPORTED, "J[%d] exceeds 2^31-1", n);
+        tmp.I[n] = desc->I[n];
+        tmp.J[n] = desc->J[n];
+        tmp.off[n] = tmp.sumI;
+        tmp.sumI += desc->I[n];
+        prodI *= (double)desc->I[n];
+        sumJ += desc->J[n];
+    }
+    if (prodI >= 4.6e18) FCS_FAIL(FCS_EUNSUPPORTED, "tensor has 2^62 or more entries");
+    tmp.Jt = sumJ - tmp.N + 1;
+    if (tmp.Jt >= ((int64_t)1 << 31) - 1) FCS_FAIL(FCS_EUNSUPPORTED, "J~ = %lld too large", (long long)tmp.Jt);
+    if (desc->L != 0) {
+        if (desc->L < tmp.Jt)
+            FCS_FAIL(FCS_EINVAL, "L=%lld is smaller than J~=%lld", (long long)desc->L, (long long)tmp.Jt);
+        if (!choose_transform(&tmp, desc->L))
+            FCS_FAIL(FCS_EUNSUPPORTED, "L=%lld is not Q*P with P a power of two in [%d,%d] and Q<=64",
+                     (long long)desc->L, FCS_MIN_FFT, FCS_MAX_FFT);
+    } else if (!choose_transform(&tmp, 0)) {
+        // very long sketches: the dense, COO and inner-product paths still work
+        tmp.P = 0;
+        tmp.Q = 0;
+        tmp.L = 0;
+    }
+    tmp.Qh = tmp.Q / 2 + 1;
+    // device layout: packed hash words, then twiddles, each 256-byte aligned
+    auto align256 = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    tmp.tab_off = 0;
+    size_t cur = align256((size_t)tmp.D * (size_t)tmp.sumI * sizeof(uint32_t));
+    tmp.twP_off = cur;
+    cur = align256(cur + (size_t)tmp.P * sizeof(float2));
+    tmp.twL_off = cur;
+    cur = align256(cur + (size_t)tmp.L * sizeof(float2));
+    tmp.total = cur;
+    fcs_plan *p = new (std::nothrow) fcs_plan(tmp);
+    if (!p) FCS_FAIL(FCS_ENOMEM, "host allocation of the plan failed");
+    *out = p;
+    return FCS_OK;
+}
+
+extern "C" size_t fcs_plan_table_bytes(fcs_plan_t p) { return p ? p->total : 0; }
+
+extern "C" fcs_status fcs_plan_bind(fcs_plan_t p, void *dev_tables, void *stream) {
+    fcs_clear_error();
+    if (!p) FCS_FAIL(FCS_EINVAL, "null plan");
+    if (!dev_tables) FCS_FAIL(FCS_EINVAL, "null table buffer");
+    if (!fcs_aligned(dev_tables, 256)) FCS_FAIL(FCS_EINVAL, "table buffer not 256-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    char *base = (char *)dev_tables;
+    HashArgs a;
+    a.tab = (uint32_t *)(base + p->tab_off);
+    a.seed_mixed = sm64_mix(p->seed);
+    for (int n = 0; n < FCS_MAX_ORDER + 1; ++n) a.off[n] = (n < p->N) ? p->off[n] : p->sumI;
+    for (int n = 0; n < FCS_MAX_ORDER; ++n) a.J[n] = (n < p->N) ? p->J[n] : 1;
+    a.N = p->N;
+    a.sumI = p->sumI;
+    a.total = (int64_t)p->D * p->sumI;
+    hash_tables_kernel<<<(unsigned)fcs_ceil_div(a.total, 256), 256, 0, s>>>(a);
+    FCS_LAUNCH_CHECK();
+    if (p->P > 0) {
+        twiddle_kernel<<<(unsigned)fcs_ceil_div(p->P, 256), 256, 0, s>>>((float2 *)(base + p->twP_off), p->P);
+        FCS_LAUNCH_CHECK();
+        twiddle_kernel<<<(unsigned)fcs_ceil_div(p->L, 256), 256, 0, s>>>((float2 *)(base + p->twL_off), p->L);
+        FCS_LAUNCH_CHECK();
+    }
+    p->tab = (const uint32_t *)(base + p->tab_off);
+    p->twP = (const float2 *)(base + p->twP_off);
+    p->twL = (const float2 *)(base + p->twL_off);
+    p->bound = true;
+    return FCS_OK;
+}
+
+extern "C" fcs_status fcs_plan_export(fcs_plan_t p, int32_t d, int32_t n, int32_t *h_host,
+                                      int8_t *s_host, void *stream) {
+    fcs_clear_error();
+    if (!p || !p->bound) FCS_FAIL(FCS_EINVAL, "plan is null or not bound");
+    if (d < 0 || d >= p->D || n < 0 || n >= p->N) FCS_FAIL(FCS_EINVAL, "d or n out of range");
+    if (!h_host || !s_host) FCS_FAIL(FCS_EINVAL, "null host output");
+    const int64_t cnt = p->I[n];
+    uint32_t *tmp = new (std::nothrow) uint32_t[cnt];
+    if (!tmp) FCS_FAIL(FCS_ENOMEM, "host allocation failed");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(tmp, p->tab + (int64_t)d * p->sumI + p->off[n], cnt * sizeof(uint32_t),
+                                  hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        delete[] tmp;
+        FCS_FAIL(FCS_EDEVICE, "table copy failed: %s", hipGetErrorString(e));
+    }
+    for (int64_t i = 0; i < cnt; ++i) {
+        h_host[i] = (int32_t)(tmp[i] & FCS_H_MASK);
+        s_host[i] = (tmp[i] & FCS_S_BIT) ? -1 : 1;
+    }
+    delete[] tmp;
+    return FCS_OK;
+}
+
+extern "C" fcs_status fcs_plan_info(fcs_plan_t p, int64_t *Jtilde, int64_t *L, int64_t *P, int32_t *Q) {
+    fcs_clear_error();
+    if (!p) FCS_FAIL(FCS_EINVAL, "null plan");
+    if (Jtilde) *Jtilde = p->Jt;
+    if (L) *L = p->L;
+    if (P) *P = p->P;
+    if (Q) *Q = p->Q;
+    return FCS_OK;
+}
+
+extern "C" int64_t fcs_plan_spec_len(fcs_plan_t p) {
+    if (!p || p->P == 0) return 0;
+    return (int64_t)p->Qh * p->P;
+}
+
+extern "C" fcs_status fcs_plan_destroy(fcs_plan_t p) {
+    delete p;
+    return FCS_OK;
+}
+
+extern "C" size_t fcs_workspace_bytes(fcs_plan_t p, int32_t op, int64_t R, int64_t P) {
+    if (!p) return 0;
+    switch (op) {
+    case FCS_OP_DENSE: return fcs_ws_dense(p);
+    case FCS_OP_COO: return fcs_ws_coo(p);
+    case FCS_OP_CP: return fcs_ws_cp(p, R);
+    case FCS_OP_INNER: return fcs_ws_inner(p);
+    case FCS_OP_FREE_MODE: return fcs_ws_free_mode(p, P);
+    case FCS_OP_SPECTRUM: return fcs_ws_spectrum(p);
+    default: return 0;
+    }
+}

@@ -1,0 +1,190 @@
+"""Python binding of libfcs: argument marshalling only.
+
+PyTorch provides device memory and streams; every step of every sketch runs
+in the HIP kernels behind the C ABI.  Tensors passed in must already be on the
+current HIP device, contiguous and of the stated dtype; outputs and
+workspaces are allocated here with torch and handed to the library.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+_I64 = ctypes.c_int64
+
+
+def _stream(stream=None) -> ctypes.c_void_p:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _need(t, dtype, name):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be on the HIP device")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+class Plan:
+    """A bound FCS plan: D sketches of an order-N tensor with mode sizes I and
+    hash lengths J, hash pairs drawn from ``seed`` (see include/fcs.h)."""
+
+    def __init__(self, I, J, D: int, seed: int, L: int = 0, device=None, stream=None):
+        self.lib = L.load()
+        self.I = tuple(int(i) for i in I)
+        self.J = tuple(int(j) for j in J)
+        self.N = len(self.I)
+        self.D = int(D)
+        self.seed = int(seed) & ((1 << 64) - 1)
+        Ia = (_I64 * self.N)(*self.I)
+        Ja = (_I64 * self.N)(*self.J)
+        desc = L.PlanDesc(self.N, Ia, Ja, self.D, self.seed, int(L))
+        h = ctypes.c_void_p()
+        L.check(self.lib.fcs_plan_create(ctypes.byref(desc), ctypes.byref(h)))
+        self._h = h
+        Jt, Lt, Pt, Qt = _I64(), _I64(), _I64(), ctypes.c_int32()
+        L.check(self.lib.fcs_plan_info(h, ctypes.byref(Jt), ctypes.byref(Lt), ctypes.byref(Pt),
+                                       ctypes.byref(Qt)))
+        self.Jt, self.L, self.P, self.Q = Jt.value, Lt.value, Pt.value, Qt.value
+        self.spec_len = int(self.lib.fcs_plan_spec_len(h))
+        self.device = torch.device("cuda") if device is None else torch.device(device)
+        nbytes = int(self.lib.fcs_plan_table_bytes(h))
+        self.tables = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+        L.check(self.lib.fcs_plan_bind(h, _ptr(self.tables), _stream(stream)))
+
+    # ------------------------------------------------------------------ utils
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self.lib.fcs_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def workspace(self, op: int, R: int = 0, P: int = 0) -> torch.Tensor:
+        n = int(self.lib.fcs_workspace_bytes(self._h, op, R, P))
+        return torch.empty(max(n, 256), dtype=torch.uint8, device=self.device)
+
+    def export(self, d: int, n: int, stream=None):
+        h = np.empty(self.I[n], dtype=np.int32)
+        s = np.empty(self.I[n], dtype=np.int8)
+        L.check(self.lib.fcs_plan_export(self._h, d, n, h.ctypes.data_as(ctypes.c_void_p),
+                                         s.ctypes.data_as(ctypes.c_void_p), _stream(stream)))
+        return h, s
+
+    def _ws(self, ws, op, R=0, P=0):
+        if ws is None:
+            ws = self.workspace(op, R, P)
+        return ws, ctypes.c_size_t(ws.numel() * ws.element_size())
+
+    # --------------------------------------------------------------- sketches
+    def sketch_dense(self, T: torch.Tensor, out=None, ws=None, stream=None) -> torch.Tensor:
+        """T: float32 with prod(I) entries in vec order (mode 0 fastest)."""
+        _need(T, torch.float32, "T")
+        if T.numel() != int(np.prod(self.I)):
+            raise ValueError("T has the wrong number of entries")
+        out = torch.empty((self.D, self.Jt), dtype=torch.float32, device=self.device) if out is None else out
+        _need(out, torch.float32, "out")
+        ws, nb = self._ws(ws, L.OP_DENSE)
+        L.check(self.lib.fcs_sketch_dense(self._h, _ptr(T), _ptr(out), _ptr(ws), nb, _stream(stream)))
+        return out
+
+    def sketch_coo(self, idx: torch.Tensor, val: torch.Tensor, out=None, ws=None, stream=None):
+        """idx: int32 N x nnz (mode-major), val: float32 nnz."""
+        _need(idx, torch.int32, "idx")
+        _need(val, torch.float32, "val")
+        nnz = val.numel()
+        if idx.shape != (self.N, nnz):
+            raise ValueError("idx must be N x nnz")
+        out = torch.empty((self.D, self.Jt), dtype=torch.float32, device=self.device) if out is None else out
+        _need(out, torch.float32, "out")
+        ws, nb = self._ws(ws, L.OP_COO)
+        L.check(self.lib.fcs_sketch_coo(self._h, nnz, _ptr(idx), _ptr(val), _ptr(out), _ptr(ws), nb,
+                                        _stream(stream)))
+        return out
+
+    def sketch_cp(self, U, lam=None, out=None, spec=None, want_out=True, want_spec=False,
+                  ws=None, stream=None):
+        """U: list of N float32 tensors of shape (R, I_n) (each row is one
+        factor column, i.e. the I_n x R factor in column-major order)."""
+        if len(U) != self.N:
+            raise ValueError("need N factors")
+        R = int(U[0].shape[0])
+        for n, u in enumerate(U):
+            _need(u, torch.float32, f"U[{n}]")
+            if tuple(u.shape) != (R, self.I[n]):
+                raise ValueError(f"U[{n}] must be R x I_n = {(R, self.I[n])}")
+        if lam is not None:
+            _need(lam, torch.float32, "lambda")
+        if want_out and out is None:
+            out = torch.empty((self.D, self.Jt), dtype=torch.float32, device=self.device)
+        if want_spec and spec is None:
+            spec = torch.empty((self.D, self.spec_len, 2), dtype=torch.float32, device=self.device)
+        ptrs = (ctypes.c_void_p * self.N)(*[u.data_ptr() for u in U])
+        ws, nb = self._ws(ws, L.OP_CP, R=R)
+        L.check(self.lib.fcs_sketch_cp(self._h, R, ptrs, _ptr(lam), _ptr(out), _ptr(spec), _ptr(ws), nb,
+                                       _stream(stream)))
+        return out, spec
+
+    def spectrum(self, y: torch.Tensor, spec=None, ws=None, stream=None):
+        _need(y, torch.float32, "y")
+        spec = torch.empty((self.D, self.spec_len, 2), dtype=torch.float32, device=self.device) \
+            if spec is None else spec
+        ws, nb = self._ws(ws, L.OP_SPECTRUM)
+        L.check(self.lib.fcs_sketch_spectrum(self._h, _ptr(y), _ptr(spec), _ptr(ws), nb, _stream(stream)))
+        return spec
+
+    # ----------------------------------------------------------- contractions
+    def contract_inner(self, a: torch.Tensor, b: torch.Tensor, ws=None, stream=None):
+        _need(a, torch.float32, "a")
+        _need(b, torch.float32, "b")
+        med = torch.empty(1, dtype=torch.float64, device=self.device)
+        per_d = torch.empty(self.D, dtype=torch.float64, device=self.device)
+        ws, nb = self._ws(ws, L.OP_INNER)
+        L.check(self.lib.fcs_contract_inner(self._h, _ptr(a), _ptr(b), _ptr(med), _ptr(per_d), _ptr(ws), nb,
+                                            _stream(stream)))
+        return med, per_d
+
+    def contract_free_mode(self, spec: torch.Tensor, free_mode: int, vecs, out=None, ws=None, stream=None):
+        """vecs: list of N entries; vecs[free_mode] is ignored (may be None);
+        the others are float32 P x I_n."""
+        _need(spec, torch.float32, "spec")
+        Pn = None
+        ptrs = (ctypes.c_void_p * self.N)()
+        for n in range(self.N):
+            if n == free_mode:
+                ptrs[n] = None
+                continue
+            v = _need(vecs[n], torch.float32, f"vecs[{n}]")
+            if Pn is None:
+                Pn = int(v.shape[0])
+            if tuple(v.shape) != (Pn, self.I[n]):
+                raise ValueError(f"vecs[{n}] must be P x I_n")
+            ptrs[n] = v.data_ptr()
+        Pn = 0 if Pn is None else Pn
+        out = torch.empty((Pn, self.I[free_mode]), dtype=torch.float64, device=self.device) \
+            if out is None else out
+        ws, nb = self._ws(ws, L.OP_FREE_MODE, P=Pn)
+        L.check(self.lib.fcs_contract_free_mode(self._h, _ptr(spec), int(free_mode), Pn, ptrs, _ptr(out),
+                                                _ptr(ws), nb, _stream(stream)))
+        return out

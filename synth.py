@@ -22,9 +22,14 @@ five benchmark configurations:
 """
 from __future__ import annotations
 
+import os
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 
 import numpy as np
+
+CHUNK = 1 << 22          # entries per independently seeded chunk
+_WORKERS = max(1, min(16, os.cpu_count() or 1))
 
 DATA_SEED = {"cp100": 1001, "dense1024": 1002, "cp10k": 1003, "batch4096": 1004,
              "serve": 1005}
@@ -52,30 +57,58 @@ def cp_factors(seed: int, I, R: int, normalize: bool = False, stream: int = 0):
     return out
 
 
+def _chunked(n: int, seed: int, stream: int, fill) -> None:
+    """Run fill(generator, start, end) over CHUNK-sized pieces of [0, n), each
+    with its own PCG64 stream (seed, stream, chunk), on a thread pool; the
+    result does not depend on the number of threads."""
+    chunks = list(range((n + CHUNK - 1) // CHUNK))
+
+    def one(k):
+        s = k * CHUNK
+        fill(rng(seed, stream, k), s, min(s + CHUNK, n))
+
+    if len(chunks) <= 1:
+        for k in chunks:
+            one(k)
+        return
+    with ThreadPoolExecutor(_WORKERS) as ex:
+        list(ex.map(one, chunks))
+
+
 def dense_tensor(seed: int, I, stream: int = 0) -> np.ndarray:
     """vec(T) (mode 0 fastest) of a float32 N(0,1) tensor, drawn directly in
-    float32."""
+    float32, chunk by chunk."""
     n = int(np.prod([int(i) for i in I]))
-    return rng(seed, stream).standard_normal(n, dtype=np.float32)
+    out = np.empty(n, dtype=np.float32)
+    _chunked(n, seed, stream, lambda g, s, e: g.standard_normal(e - s, dtype=np.float32, out=out[s:e]))
+    return out
 
 
 def integer_tensor(seed: int, I, lo: int = -3, hi: int = 3, stream: int = 0):
     """Small-integer tensor (float32) whose every partial sum is exact."""
     n = int(np.prod([int(i) for i in I]))
-    return rng(seed, stream).integers(lo, hi + 1, size=n).astype(np.float32)
+    out = np.empty(n, dtype=np.float32)
+
+    def fill(g, s, e):
+        out[s:e] = g.integers(lo, hi + 1, size=e - s)
+
+    _chunked(n, seed, stream, fill)
+    return out
 
 
-def bernoulli_coo(seed: int, T_vec: np.ndarray, I, density: float,
-                  chunk: int = 1 << 26, stream: int = 1):
-    """Keep each linear index with probability ``density`` (seeded); returns
-    (idx int32 [N][nnz] mode-major, val float32 [nnz]) sorted by linear index."""
-    g = rng(seed, stream)
+def bernoulli_coo(seed: int, T_vec: np.ndarray, I, density: float, stream: int = 1):
+    """Keep each linear index with probability ``density`` (seeded, chunked);
+    returns (idx int32 [N][nnz] mode-major, val float32 [nnz]) sorted by
+    linear index."""
     I = [int(i) for i in I]
     total = T_vec.size
-    keep = []
-    for start in range(0, total, chunk):
-        m = g.random(min(chunk, total - start), dtype=np.float32) < density
-        keep.append(np.flatnonzero(m).astype(np.int64) + start)
+    nchunks = (total + CHUNK - 1) // CHUNK
+    keep = [None] * nchunks
+
+    def fill(g, s, e):
+        keep[s // CHUNK] = np.flatnonzero(g.random(e - s, dtype=np.float32) < density).astype(np.int64) + s
+
+    _chunked(total, seed, stream, fill)
     lin = np.concatenate(keep) if keep else np.zeros(0, np.int64)
     val = T_vec[lin].astype(np.float32)
     idx = np.empty((len(I), lin.size), dtype=np.int32)
