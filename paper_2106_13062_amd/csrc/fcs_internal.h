@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <climits>
 #include <cstdio>
 #include <string>
 
@@ -32,6 +33,10 @@ struct fcs_plan {
     const uint32_t *tab = nullptr;     // D x sumI packed hash words
     const float2 *twP = nullptr;       // exp(-2 pi i k / P), k < P
     const float2 *twL = nullptr;       // exp(-2 pi i k / L), k < L
+    // largest number of mode-0 indices that share one h_0 value, over all
+    // sketches (bounds the additions one row makes to one bin); INT32_MAX
+    // when too large to evaluate on the host
+    int m0 = INT32_MAX;
     bool bound = false;
 };
 

@@ -2,10 +2,12 @@
 // device, status strings and small shared launch helpers.
 #include "fcs_internal.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstring>
 #include <new>
+#include <vector>
 
 // ---------------------------------------------------------------------------
 // error state (per host thread)
@@ -217,6 +219,34 @@ extern "C" fcs_status fcs_plan_create(const fcs_plan_desc *desc, fcs_plan_t *out
 
 extern "C" size_t fcs_plan_table_bytes(fcs_plan_t p) { return p ? p->total : 0; }
 
+// Largest multiplicity of h_0 values over all sketches, evaluated with the
+// same hash function on the host (small plans only).
+static int mode0_multiplicity(const fcs_plan *p) {
+    const int64_t I0 = p->I[0];
+    if ((double)I0 * (double)p->D > 268435456.0) return INT32_MAX;
+    const uint64_t sm = sm64_mix(p->seed);
+    std::vector<uint32_t> h((size_t)I0);
+    int best = 0;
+    for (int d = 0; d < p->D; ++d) {
+        const uint64_t key = sm64_mix(sm + ((uint64_t)d << 16) + 0u);
+        for (int64_t i = 0; i < I0; ++i) {
+            const uint64_t y = sm64_mix(key + (uint64_t)i);
+            h[(size_t)i] = (uint32_t)(((y >> 32) * (uint64_t)p->J[0]) >> 32);
+        }
+        std::sort(h.begin(), h.end());
+        int run = 1;
+        for (size_t i = 1; i <= h.size(); ++i) {
+            if (i < h.size() && h[i] == h[i - 1]) {
+                ++run;
+            } else {
+                best = std::max(best, run);
+                run = 1;
+            }
+        }
+    }
+    return std::max(best, 1);
+}
+
 extern "C" fcs_status fcs_plan_bind(fcs_plan_t p, void *dev_tables, void *stream) {
     fcs_clear_error();
     if (!p) FCS_FAIL(FCS_EINVAL, "null plan");
@@ -240,6 +270,7 @@ extern "C" fcs_status fcs_plan_bind(fcs_plan_t p, void *dev_tables, void *stream
         twiddle_kernel<<<(unsigned)fcs_ceil_div(p->L, 256), 256, 0, s>>>((float2 *)(base + p->twL_off), p->L);
         FCS_LAUNCH_CHECK();
     }
+    p->m0 = mode0_multiplicity(p);
     p->tab = (const uint32_t *)(base + p->tab_off);
     p->twP = (const float2 *)(base + p->twP_off);
     p->twL = (const float2 *)(base + p->twL_off);

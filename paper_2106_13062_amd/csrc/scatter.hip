@@ -4,62 +4,95 @@
 // H = sum_n h_n(i_n) of each of the D sketches.  The long hash (H, S) of
 // Definition 4 is never built: only the N short tables are read.
 //
-// Dense kernel design (gfx950):
+// Why integer bins.  On gfx950 an LDS float atomic add (ds_add_f32) retires
+// about 0.3 lanes per clock per CU, while ds_add_u32 retires about 12 in the
+// access pattern of this kernel (ds_add_f64 about 3).  The bins are therefore
+// 32-bit fixed-point integers: each workgroup picks a power-of-two scale 2^F
+// from the largest magnitude among its first rows, adds round(x 2^F) with
+// ds_add_u32, and converts the bins back to float (exactly, by 2^-F) into
+// per-thread register accumulators at the end of every "period" of rows.
+//   * |round(x 2^F)| <= 2^22 - 1 for every element taken on this path; an
+//     element beyond (or a NaN / Inf) is added with a float atomic to the HBM
+//     sketch instead, so nothing is lost.
+//   * a row adds at most m0 elements to one bin, m0 the largest number of
+//     mode-0 indices sharing one h_0 value (computed when the plan is bound);
+//     a period of P rows with P * m0 <= 511 therefore keeps every bin below
+//     2^31 in magnitude: no overflow is possible.
+//   * the largest first-row magnitude maps into [2^19, 2^20), so the rounding
+//     step is at most 2^-19 of it: about 2e-6 relative error on a bin of
+//     Gaussian data, against 1e-5 allowed.  Integer-valued data with small
+//     magnitudes is exact.
+//
+// Dense kernel layout (gfx950, wave64):
 //  * vec(T) is a sequence of rows along mode 0 (I_0 contiguous floats).  Along
-//    a row, H = c(row) + h_0(i_0): the offset c and the row sign depend only
-//    on the row, so they are wave-uniform scalars, and the per-column part
-//    h_0 / s_0 of a wave's columns is fixed for all rows it visits.
-//  * A wave owns a 512-column segment of the rows it visits (8 floats per
-//    lane, two 16-byte loads); its lanes keep, for every sketch of the
-//    workgroup, the LDS byte address of bin h_0(i_0) and the sign mask of
-//    s_0(i_0) in registers.  Per element and sketch the hot loop is one
-//    v_add (address + row offset), one v_bitop3 (value ^ column sign ^ row
-//    sign) and one LDS float atomic add.
-//  * Bins are privatised in LDS per workgroup.  When N >= 2 a workgroup's rows
-//    share the last-mode index, so its bins lie in the window
-//    h_{N-1}(i_{N-1}) + [0, J~ - J_{N-1} + 1) and only that window is held;
-//    the sketches are split into groups of DG so DG windows fit in LDS.
-//    At the end the window is added to the HBM sketch with coalesced float
-//    atomics.
-//  * The two (or more) sketch groups of one slab are dispatched to the same
-//    XCD back to back (workgroups go round-robin over the 8 XCDs), so the
-//    second read of the slab is served from that XCD's L2.
+//    a row H = c(row) + h_0(i_0), so the offset c and the row sign are
+//    wave-uniform and the column part h_0 / s_0 is fixed for every row a wave
+//    visits.  A wave owns a 256-column segment (one 16-byte load per lane) of
+//    the rows it visits; its lanes keep the LDS byte address of bin h_0(i_0)
+//    and the sign of s_0(i_0) of every sketch of the group in registers.  Per
+//    element and sketch: one v_bitop3 (sign), one v_cvt_rpi (round), one
+//    v_add (address) and one ds_add_u32.
+//  * When N >= 2 a workgroup's rows share the last-mode index, so its bins lie
+//    in h_{N-1}(i_{N-1}) + [0, J~ - J_{N-1} + 1) and only that window is held
+//    (the last mode's sign is applied at the flush).  Sketches are split into
+//    groups of DG windows that fit in LDS; the groups of one slab are
+//    dispatched back to back onto one XCD (workgroups go round-robin over the
+//    8 XCDs) so the second read of the slab hits that XCD's L2.
 #include "fcs_internal.h"
 
 #include <algorithm>
 
 namespace {
 
-constexpr int DS_THREADS = 1024;     // 16 waves
+constexpr int DS_THREADS = 1024;        // 16 waves
 constexpr int DS_WAVES = DS_THREADS / 64;
-constexpr int SEG = 512;             // columns of a wave segment
+constexpr int SEG = 256;                // columns of a wave segment
 constexpr int NXCD = 8;
+constexpr int MAXACC = 32;              // register accumulators per thread
+constexpr int SCALE_TOP = 20;           // first-rows max maps below 2^20
+constexpr float QLIM = 4194302.0f;      // 2^22 - 2: larger |x 2^F| -> float path
+constexpr int ADD_BOUND = 511;          // P * m0 <= 511 keeps |bin| < 2^31
 
 struct DenseArgs {
     const float *T;
     float *out;
     const uint32_t *tab;
-    int64_t I[FCS_MAX_ORDER];
+    int32_t I[FCS_MAX_ORDER];
     int64_t off[FCS_MAX_ORDER];
     int64_t sumI;
     int64_t I0;
-    int64_t rows;          // prod_{n>=1} I_n
-    int64_t slab_rows;     // rows sharing one last-mode index (windowed mode)
-    int64_t block_rows;    // rows per workgroup block
+    int64_t rows;            // prod_{n>=1} I_n
+    int64_t slab_rows;       // rows sharing one last-mode index
+    int64_t block_rows;      // rows per row block
     int64_t blocks_per_slab;
-    int64_t nblocks;
+    int64_t row_blocks;
     int64_t Jt;
-    int64_t W;             // bins held per sketch in LDS
+    int W;                   // bins held per sketch in LDS
     int N;
     int D;
-    int ngroups;           // groups of DG sketches in this launch
-    int d_first;           // first sketch of this launch
-    int windowed;          // 1: window anchored at h_{N-1}(i_{N-1})
-    int segs;              // ceil(I0 / SEG)
+    int ngroups;             // groups of DG sketches in this launch
+    int d_first;             // first sketch of this launch
+    int windowed;            // 1: window anchored at h_{N-1}(i_{N-1})
+    int segs;                // ceil(I0 / SEG)
+    int seg_blocks;          // column blocks
+    int segs_per_block;
+    int period;              // rows per flush period
+    int nrow_modes;          // modes 1..nrow_modes vary along a block's rows
 };
 
-// Map the flat block id to (row block, sketch group) so that all groups of a
-// row block land on one XCD consecutively.
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    uint32_t r;
+    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
+// round to nearest (ties up) and convert: one VALU op
+__device__ __forceinline__ int cvt_rpi(float x) {
+    int r;
+    asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+
 __device__ inline void dense_block_map(const DenseArgs &a, int64_t bid, int64_t &blk, int &grp) {
     const int64_t span = (int64_t)NXCD * a.ngroups;
     const int64_t super = bid / span;
@@ -68,129 +101,148 @@ __device__ inline void dense_block_map(const DenseArgs &a, int64_t bid, int64_t 
     blk = super * NXCD + (rem % NXCD);
 }
 
-// value ^ column sign ^ row sign in one VALU op (three-input xor, gfx950).
-__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
-    uint32_t r;
-    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "v"(c));
-    return r;
-}
+// Row-mode state of one wave: the mixed-radix index (i_1, ..., i_NV) of its
+// current row and the table pointers of those modes for every sketch.
+template <int DG, int NV>
+struct RowWalk {
+    int idx[NV > 0 ? NV : 1];
+    const uint32_t *tp[NV > 0 ? NV : 1][DG];
 
-// Scatter one row segment of 8 values per lane into the LDS windows of the
-// DG sketches.  Row offset C[d] (bytes) and row sign R[d] are wave-uniform.
-// Per element and sketch: one v_bitop3, one v_add and one ds_add_f32.
-template <int DG, bool CHECK>
-__device__ __forceinline__ void scatter_row(float *bins, const float (&x)[8], const uint32_t (&A)[DG][8],
-                                            const uint32_t (&M)[DG][8], const bool (&valid)[8],
-                                            const uint32_t (&C)[DG], const uint32_t (&R)[DG]) {
+    __device__ __forceinline__ void init(const DenseArgs &a, int d0, int64_t r) {
 #pragma unroll
-    for (int d = 0; d < DG; ++d) {
+        for (int n = 0; n < NV; ++n) {
+            idx[n] = (int)(r % a.I[n + 1]);
+            r /= a.I[n + 1];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            if (!CHECK || valid[e]) {
-                const float v = __uint_as_float(xor3(__float_as_uint(x[e]), M[d][e], R[d]));
-                float *dst = reinterpret_cast<float *>(reinterpret_cast<char *>(bins) + (A[d][e] + C[d]));
-                __hip_atomic_fetch_add(dst, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            for (int d = 0; d < DG; ++d) tp[n][d] = a.tab + (int64_t)(d0 + d) * a.sumI + a.off[n + 1];
+        }
+    }
+    __device__ __forceinline__ void advance(const DenseArgs &a, int step) {
+        int carry = step;
+#pragma unroll
+        for (int n = 0; n < NV; ++n) {
+            if (carry) {
+                const int In = a.I[n + 1];
+                const int t = idx[n] + carry;
+                if (t < In) {
+                    idx[n] = t;
+                    carry = 0;
+                } else {
+                    idx[n] = t % In;
+                    carry = t / In;
+                }
             }
         }
     }
-}
-
-// Row offset (bytes) and row sign of every sketch of the group, from the
-// hash words of modes 1..nvar-1 at the decoded row index.
-template <int DG>
-__device__ __forceinline__ void row_hash(const DenseArgs &a, int d0, int nvar, const int (&idx)[FCS_MAX_ORDER],
-                                         uint32_t (&C)[DG], uint32_t (&R)[DG]) {
-    uint32_t w[FCS_MAX_ORDER - 1][DG];
+    // row offset (bytes) and row sign of every sketch of the group
+    __device__ __forceinline__ void hash(uint32_t (&C)[DG], uint32_t (&R)[DG]) const {
 #pragma unroll
-    for (int n = 1; n < FCS_MAX_ORDER; ++n) {
-        if (n < nvar) {
-#pragma unroll
-            for (int d = 0; d < DG; ++d)
-                w[n - 1][d] = __builtin_nontemporal_load(a.tab + (int64_t)(d0 + d) * a.sumI + a.off[n] + idx[n]);
+        for (int d = 0; d < DG; ++d) {
+            C[d] = 0;
+            R[d] = 0;
         }
-    }
 #pragma unroll
-    for (int d = 0; d < DG; ++d) {
-        C[d] = 0;
-        R[d] = 0;
-    }
-#pragma unroll
-    for (int n = 1; n < FCS_MAX_ORDER; ++n) {
-        if (n < nvar) {
+        for (int n = 0; n < NV; ++n) {
 #pragma unroll
             for (int d = 0; d < DG; ++d) {
-                C[d] += (w[n - 1][d] & FCS_H_MASK) * 4u;
-                R[d] ^= w[n - 1][d] & FCS_S_BIT;
+                const uint32_t w = tp[n][d][idx[n]];
+                C[d] += (w & FCS_H_MASK) * 4u;
+                R[d] ^= w & FCS_S_BIT;
             }
         }
     }
-}
-
-__device__ __forceinline__ void advance_rows(const DenseArgs &a, int nvar, int step, int (&idx)[FCS_MAX_ORDER]) {
-    int carry = step;
-#pragma unroll
-    for (int n = 1; n < FCS_MAX_ORDER; ++n) {
-        if (n < nvar && carry) {
-            const uint32_t In = (uint32_t)a.I[n];
-            const uint32_t t = (uint32_t)idx[n] + (uint32_t)carry;
-            if (t < In) {
-                idx[n] = (int)t;
-                carry = 0;
-            } else {
-                idx[n] = (int)(t % In);
-                carry = (int)(t / In);
-            }
-        }
-    }
-}
+};
 
 template <bool VEC4, bool FULL>
-__device__ __forceinline__ void load_row(const float *row, int lane, const bool (&valid)[8], float (&x)[8]) {
+__device__ __forceinline__ void load_seg(const float *row, int lane, const bool (&valid)[4], float (&x)[4]) {
     if (FULL && VEC4) {
-        const float4 q0 = *reinterpret_cast<const float4 *>(row + lane * 4);
-        const float4 q1 = *reinterpret_cast<const float4 *>(row + 256 + lane * 4);
-        x[0] = q0.x; x[1] = q0.y; x[2] = q0.z; x[3] = q0.w;
-        x[4] = q1.x; x[5] = q1.y; x[6] = q1.z; x[7] = q1.w;
+        const float4 q = *reinterpret_cast<const float4 *>(row + lane * 4);
+        x[0] = q.x; x[1] = q.y; x[2] = q.z; x[3] = q.w;
     } else {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) x[e] = (FULL || valid[e]) ? row[(e >> 2) * 256 + lane * 4 + (e & 3)] : 0.f;
+        for (int e = 0; e < 4; ++e) x[e] = (FULL || valid[e]) ? row[lane * 4 + e] : 0.f;
     }
 }
 
-// All rows [r_first, r1) with stride wps of one segment; the next row's hash
-// words and values are in flight while the current row is scattered.
-template <int DG, bool VEC4, bool FULL>
-__device__ __forceinline__ void segment_rows(const DenseArgs &a, float *bins, int d0, int nvar, int seg, int lane,
-                                             int64_t r_first, int64_t r1, int wps, const uint32_t (&A)[DG][8],
-                                             const uint32_t (&M)[DG][8], const bool (&valid)[8]) {
-    if (r_first >= r1) return;
-    int idx[FCS_MAX_ORDER];
-    {
-        int64_t rem = r_first;
+// Out-of-range or non-finite entries: float atomics into the HBM sketch, with
+// every sign including the slab's last-mode sign.
+template <int DG, bool CHECK>
+__device__ __forceinline__ void scatter_slow(const DenseArgs &a, const float (&x)[4], float scale, int d0,
+                                                       const uint32_t (&A)[DG][4], const uint32_t (&M)[DG][4],
+                                                       const bool (&valid)[4], const uint32_t (&C)[DG],
+                                                       const uint32_t (&R)[DG], const int (&base)[DG],
+                                                       const uint32_t (&wsign)[DG]) {
 #pragma unroll
-        for (int n = 1; n < FCS_MAX_ORDER; ++n) {
-            idx[n] = 0;
-            if (n < nvar) {
-                idx[n] = (int)(rem % a.I[n]);
-                rem /= a.I[n];
+    for (int e = 0; e < 4; ++e) {
+        const float xe = x[e];
+        if ((!CHECK || valid[e]) && !(fabsf(xe * scale) < QLIM)) {
+#pragma unroll
+            for (int d = 0; d < DG; ++d) {
+                const int bin = (int)((A[d][e] + C[d]) / 4u) - d * a.W;
+                const uint32_t sg = M[d][e] ^ R[d] ^ wsign[d];
+                unsafeAtomicAdd(a.out + (int64_t)(d0 + d) * a.Jt + base[d] + bin,
+                                __uint_as_float(__float_as_uint(xe) ^ sg));
             }
         }
     }
+}
+
+// Add one row segment (4 values per lane) to the DG fixed-point windows.
+template <int DG, bool CHECK>
+__device__ __forceinline__ void scatter_seg(const DenseArgs &a, uint32_t *qbins, const float (&x)[4], float scale,
+                                            int d0, const uint32_t (&A)[DG][4], const uint32_t (&M)[DG][4],
+                                            const bool (&valid)[4], const uint32_t (&C)[DG],
+                                            const uint32_t (&R)[DG], const int (&base)[DG],
+                                            const uint32_t (&wsign)[DG]) {
+    float xs[4];
+    bool slow = false;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        xs[e] = x[e] * scale;
+        const bool ok = fabsf(xs[e]) < QLIM;     // false for NaN / Inf too
+        slow |= (!ok) && (!CHECK || valid[e]);
+        xs[e] = ok ? xs[e] : 0.f;
+    }
+#pragma unroll
+    for (int d = 0; d < DG; ++d) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            if (!CHECK || valid[e]) {
+                const int q = cvt_rpi(__uint_as_float(xor3(__float_as_uint(xs[e]), M[d][e], R[d])));
+                uint32_t *dst = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(qbins) + (A[d][e] + C[d]));
+                __hip_atomic_fetch_add(dst, (uint32_t)q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+        }
+    }
+    if (__builtin_expect(slow, 0)) scatter_slow<DG, CHECK>(a, x, scale, d0, A, M, valid, C, R, base, wsign);
+}
+
+// Rows [r_first, r1) with stride wps of one segment; the next row's hash words
+// and values are in flight while the current row is scattered.
+template <int DG, int NV, bool VEC4, bool FULL>
+__device__ __forceinline__ void segment_rows(const DenseArgs &a, uint32_t *qbins, float scale, int d0, int seg,
+                                             int lane, int64_t r_first, int64_t r1, int wps,
+                                             const uint32_t (&A)[DG][4], const uint32_t (&M)[DG][4],
+                                             const bool (&valid)[4], const int (&base)[DG],
+                                             const uint32_t (&wsign)[DG]) {
+    if (r_first >= r1) return;
+    RowWalk<DG, NV> walk;
+    walk.init(a, d0, r_first);
     const float *Tseg = a.T + (int64_t)seg * SEG;
     uint32_t C[DG], R[DG];
-    float x[8];
-    row_hash<DG>(a, d0, nvar, idx, C, R);
-    load_row<VEC4, FULL>(Tseg + r_first * a.I0, lane, valid, x);
+    float x[4];
+    walk.hash(C, R);
+    load_seg<VEC4, FULL>(Tseg + r_first * a.I0, lane, valid, x);
     for (int64_t r = r_first; r < r1; r += wps) {
         const int64_t rn = r + wps;
         uint32_t Cn[DG], Rn[DG];
-        float xn[8];
+        float xn[4];
         if (rn < r1) {
-            advance_rows(a, nvar, wps, idx);
-            row_hash<DG>(a, d0, nvar, idx, Cn, Rn);
-            load_row<VEC4, FULL>(Tseg + rn * a.I0, lane, valid, xn);
+            walk.advance(a, wps);
+            walk.hash(Cn, Rn);
+            load_seg<VEC4, FULL>(Tseg + rn * a.I0, lane, valid, xn);
         }
-        scatter_row<DG, !FULL>(bins, x, A, M, valid, C, R);
+        scatter_seg<DG, !FULL>(a, qbins, x, scale, d0, A, M, valid, C, R, base, wsign);
         if (rn < r1) {
 #pragma unroll
             for (int d = 0; d < DG; ++d) {
@@ -198,85 +250,150 @@ __device__ __forceinline__ void segment_rows(const DenseArgs &a, float *bins, in
                 R[d] = Rn[d];
             }
 #pragma unroll
-            for (int e = 0; e < 8; ++e) x[e] = xn[e];
+            for (int e = 0; e < 4; ++e) x[e] = xn[e];
         }
     }
 }
 
-template <int DG, bool VEC4>
+template <int DG, int NV, bool VEC4>
 __global__ __launch_bounds__(DS_THREADS) void dense_scatter_kernel(DenseArgs a) {
-    extern __shared__ float bins[];   // DG x W
+    extern __shared__ uint32_t qbins[];     // DG x W fixed-point bins
+    __shared__ float wave_max[DS_WAVES];
     int64_t blk;
     int grp;
     dense_block_map(a, blockIdx.x, blk, grp);
-    if (blk >= a.nblocks) return;
-    const int d0 = a.d_first + grp * DG;   // this launch covers whole groups of DG sketches
+    if (blk >= a.row_blocks * a.seg_blocks) return;
+    const int64_t rblk = blk / a.seg_blocks;
+    const int sblk = (int)(blk - rblk * a.seg_blocks);
+    const int d0 = a.d_first + grp * DG;
 
-    // row range of this block
+    // rows and column segments of this block
     int64_t r0, r1;
     if (a.windowed) {
-        const int64_t slab = blk / a.blocks_per_slab;
-        const int64_t sub = blk - slab * a.blocks_per_slab;
+        const int64_t slab = rblk / a.blocks_per_slab;
+        const int64_t sub = rblk - slab * a.blocks_per_slab;
         r0 = slab * a.slab_rows + sub * a.block_rows;
         r1 = min(r0 + a.block_rows, (slab + 1) * a.slab_rows);
     } else {
-        r0 = blk * a.block_rows;
+        r0 = rblk * a.block_rows;
         r1 = min(r0 + a.block_rows, a.rows);
     }
+    const int s0 = sblk * a.segs_per_block;
+    const int s1 = min(a.segs, s0 + a.segs_per_block);
+    const int nseg = s1 - s0;
 
-    // window base per sketch: the last-mode hash of this slab
+    // window base and sign per sketch: the last-mode hash pair of the slab
     int base[DG];
-    const int last = a.N - 1;
+    uint32_t wsign[DG];
     const int64_t ilast = (a.windowed && a.N >= 2) ? (r0 / a.slab_rows) : 0;
 #pragma unroll
     for (int d = 0; d < DG; ++d) {
         base[d] = 0;
-        if (a.windowed && a.N >= 2)
-            base[d] = (int)(a.tab[(int64_t)(d0 + d) * a.sumI + a.off[last] + ilast] & FCS_H_MASK);
+        wsign[d] = 0;
+        if (a.windowed && a.N >= 2) {
+            const uint32_t p = a.tab[(int64_t)(d0 + d) * a.sumI + a.off[a.N - 1] + ilast];
+            base[d] = (int)(p & FCS_H_MASK);
+            wsign[d] = p & FCS_S_BIT;
+        }
     }
 
-    const int W = (int)a.W;
-    for (int k = threadIdx.x; k < DG * W; k += DS_THREADS) bins[k] = 0.f;
-    __syncthreads();
+    const int W = a.W;
+    for (int k = threadIdx.x; k < DG * W; k += DS_THREADS) qbins[k] = 0u;
 
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
     const int lane = threadIdx.x % 64;
-    const int wps = max(1, DS_WAVES / a.segs);             // waves per segment
-    const int nvar = a.windowed ? a.N - 1 : a.N;           // modes 1..nvar-1 vary per row
 
-    for (int sidx = wave; sidx < a.segs * wps; sidx += DS_WAVES) {
-        const int seg = sidx % a.segs;
-        const int rl = sidx / a.segs;
-        // per-lane column data of this segment, kept in registers for all rows
-        uint32_t A[DG][8], M[DG][8];
-        bool valid[8];
+    // scale: largest magnitude among up to 16 leading rows (first 4096
+    // columns of the block's segments), mapped into [2^19, 2^20)
+    {
+        const int64_t nrows = r1 - r0;
+        const int64_t r = r0 + (wave % nrows);
+        const int64_t c0 = (int64_t)s0 * SEG;
+        const int64_t c1 = min<int64_t>(min<int64_t>((int64_t)s1 * SEG, a.I0), c0 + 4096);
+        float m = 0.f;
+        for (int64_t c = c0 + lane; c < c1; c += 64) m = fmaxf(m, fabsf(a.T[r * a.I0 + c]));
+        // NaN / Inf in the sample are ignored here; they take the float path
+        if (!(m <= 3.0e38f)) m = 0.f;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int64_t col = (int64_t)seg * SEG + (e >> 2) * 256 + lane * 4 + (e & 3);
-            valid[e] = col < a.I0;
-#pragma unroll
-            for (int d = 0; d < DG; ++d) {
-                const uint32_t p = valid[e] ? a.tab[(int64_t)(d0 + d) * a.sumI + col] : 0u;
-                A[d][e] = (uint32_t)((d * W + (int)(p & FCS_H_MASK)) * 4);
-                M[d][e] = p & FCS_S_BIT;
-            }
-        }
-        if ((int64_t)(seg + 1) * SEG <= a.I0)   // wave-uniform
-            segment_rows<DG, VEC4, true>(a, bins, d0, nvar, seg, lane, r0 + rl, r1, wps, A, M, valid);
-        else
-            segment_rows<DG, VEC4, false>(a, bins, d0, nvar, seg, lane, r0 + rl, r1, wps, A, M, valid);
+        for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+        if (lane == 0) wave_max[wave] = m;
     }
     __syncthreads();
-    // flush the window into the HBM sketch
-    for (int k = threadIdx.x; k < DG * W; k += DS_THREADS) {
-        const int d = k / W;
-        const int j = k - d * W;
-        const float v = bins[k];
-        if (v != 0.f) unsafeAtomicAdd(a.out + (int64_t)(d0 + d) * a.Jt + base[d] + j, v);
+    float M0 = 0.f;
+#pragma unroll
+    for (int w = 0; w < DS_WAVES; ++w) M0 = fmaxf(M0, wave_max[w]);
+    int F = SCALE_TOP - 1;
+    if (M0 > 0.f) F = SCALE_TOP - __builtin_amdgcn_frexp_expf(M0);
+    F = max(-100, min(100, F));
+    const float scale = ldexpf(1.0f, F);
+    const float inv = ldexpf(1.0f, -F);
+
+    float acc[MAXACC];
+#pragma unroll
+    for (int m = 0; m < MAXACC; ++m) acc[m] = 0.f;
+
+    const int wps = max(1, DS_WAVES / nseg);             // waves per segment
+    for (int64_t p0 = r0; p0 < r1; p0 += a.period) {
+        const int64_t p1 = min<int64_t>(p0 + a.period, r1);
+        for (int sidx = wave; sidx < nseg * wps; sidx += DS_WAVES) {
+            const int seg = s0 + sidx % nseg;
+            const int rl = sidx / nseg;
+            uint32_t A[DG][4], M[DG][4];
+            bool valid[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t col = (int64_t)seg * SEG + lane * 4 + e;
+                valid[e] = col < a.I0;
+#pragma unroll
+                for (int d = 0; d < DG; ++d) {
+                    const uint32_t p = valid[e] ? a.tab[(int64_t)(d0 + d) * a.sumI + col] : 0u;
+                    A[d][e] = (uint32_t)((d * W + (int)(p & FCS_H_MASK)) * 4);
+                    M[d][e] = p & FCS_S_BIT;
+                }
+            }
+            if ((int64_t)(seg + 1) * SEG <= a.I0)
+                segment_rows<DG, NV, VEC4, true>(a, qbins, scale, d0, seg, lane, p0 + rl, p1, wps, A, M, valid,
+                                                 base, wsign);
+            else
+                segment_rows<DG, NV, VEC4, false>(a, qbins, scale, d0, seg, lane, p0 + rl, p1, wps, A, M, valid,
+                                                  base, wsign);
+        }
+        __syncthreads();
+        // period flush: integer bins -> float register accumulators (exact
+        // scaling by 2^-F), bins back to zero
+#pragma unroll
+        for (int m = 0; m < MAXACC; ++m) {
+            const int k = threadIdx.x + m * DS_THREADS;
+            if (k < DG * W) {
+                acc[m] += (float)(int)qbins[k] * inv;
+                qbins[k] = 0u;
+            }
+        }
+        __syncthreads();
+    }
+    // add the window to the HBM sketch, with the slab's last-mode sign
+#pragma unroll
+    for (int m = 0; m < MAXACC; ++m) {
+        const int k = threadIdx.x + m * DS_THREADS;
+        if (k < DG * W) {
+            const int d = k / W;
+            const int j = k - d * W;
+            int bd = base[0];
+            uint32_t sd = wsign[0];
+#pragma unroll
+            for (int dd = 1; dd < DG; ++dd) {
+                if (d == dd) {
+                    bd = base[dd];
+                    sd = wsign[dd];
+                }
+            }
+            const float v = __uint_as_float(__float_as_uint(acc[m]) ^ sd);
+            if (v != 0.f) unsafeAtomicAdd(a.out + (int64_t)(d0 + d) * a.Jt + bd + j, v);
+        }
     }
 }
 
-// Fallback when not even one sketch window fits in LDS: global atomics.
+// Fallback when not even one sketch window fits in LDS: float atomics in HBM.
 __global__ __launch_bounds__(256) void dense_scatter_global_kernel(DenseArgs a) {
     const int64_t total = a.rows * a.I0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -296,96 +413,122 @@ __global__ __launch_bounds__(256) void dense_scatter_global_kernel(DenseArgs a) 
                 H += p & FCS_H_MASK;
                 S ^= p & FCS_S_BIT;
             }
-            unsafeAtomicAdd(a.out + (int64_t)d * a.Jt + H, __int_as_float(__float_as_int(x) ^ S));
+            unsafeAtomicAdd(a.out + (int64_t)d * a.Jt + H, __uint_as_float(__float_as_uint(x) ^ S));
         }
     }
 }
 
 struct DenseLaunch {
-    int dg = 0;            // 0: global fallback
+    int dg = 0;              // 0: global fallback
     bool windowed = false;
     int64_t W = 0;
-    int64_t slab_rows = 0, block_rows = 0, blocks_per_slab = 0, nblocks = 0;
+    int64_t slab_rows = 0, block_rows = 0, blocks_per_slab = 0, row_blocks = 0;
+    int segs = 0, seg_blocks = 1, segs_per_block = 0;
 };
 
 DenseLaunch plan_dense(const fcs_plan *p) {
     DenseLaunch L;
-    const int64_t rows = p->sumI > 0 ? [&] {
-        int64_t r = 1;
-        for (int n = 1; n < p->N; ++n) r *= p->I[n];
-        return r;
-    }() : 1;
+    int64_t rows = 1;
+    for (int n = 1; n < p->N; ++n) rows *= p->I[n];
     const int64_t I0 = p->I[0];
-    const size_t budget = FCS_LDS_BYTES - 1024;
-    // windowed: workgroups never span two values of the last mode
+    L.segs = (int)fcs_ceil_div(I0, SEG);
+    const size_t budget = std::min<size_t>(FCS_LDS_BYTES - 1024, (size_t)MAXACC * DS_THREADS * 4);
+    const int64_t total = rows * I0;
+    // windowed: a row block never spans two values of the last mode
+    // a single row may not add more than ADD_BOUND elements to one bin
+    if (p->m0 > ADD_BOUND) return L;
     if (p->N >= 2) {
         const int64_t Wwin = p->Jt - p->J[p->N - 1] + 1;
         const int64_t slab_rows = rows / p->I[p->N - 1];
-        // worth it when a slab holds many more elements than window bins
         if ((double)slab_rows * (double)I0 >= 16.0 * (double)Wwin) {
-            int dg = (int)std::min<int64_t>(4, budget / (4 * Wwin));
+            int dg = (int)std::min<int64_t>(4, (int64_t)(budget / (4 * Wwin)));
             dg = std::min(dg, p->D);
             if (dg >= 1) {
                 L.dg = dg;
                 L.windowed = true;
                 L.W = Wwin;
                 L.slab_rows = slab_rows;
-                // split a slab into several blocks only when there are too
-                // few slabs to fill the chip, and never below 128 elements
-                // per bin (each block ends with one flush of its window)
+                // split a slab only when there are too few slabs to fill the
+                // chip, and keep >= 128 elements per bin per block (each block
+                // ends with one flush of its window)
                 const int64_t elems = slab_rows * I0;
                 int64_t bps = fcs_ceil_div(1024, p->I[p->N - 1]);
                 bps = std::min<int64_t>(bps, std::max<int64_t>(1, elems / (128 * Wwin)));
                 bps = std::max<int64_t>(1, std::min<int64_t>(bps, slab_rows));
                 L.block_rows = fcs_ceil_div(slab_rows, bps);
                 L.blocks_per_slab = fcs_ceil_div(slab_rows, L.block_rows);
-                L.nblocks = L.blocks_per_slab * p->I[p->N - 1];
+                L.row_blocks = L.blocks_per_slab * p->I[p->N - 1];
+                L.seg_blocks = 1;
+                L.segs_per_block = L.segs;
                 return L;
             }
         }
     }
-    int dg = (int)std::min<int64_t>(4, budget / (4 * p->Jt));
+    int dg = (int)std::min<int64_t>(4, (int64_t)(budget / (4 * p->Jt)));
     dg = std::min(dg, p->D);
     if (dg < 1) return L;   // global fallback
     L.dg = dg;
     L.windowed = false;
     L.W = p->Jt;
     L.slab_rows = rows;
-    // enough blocks to fill the chip, but each block sketches many more
-    // elements than it has bins
-    const int64_t total = rows * I0;
+    // enough blocks to fill the chip, each sketching many more elements than
+    // it has bins; few long rows are split by column segments instead
     int64_t nb = std::max<int64_t>(1, std::min<int64_t>(total / std::max<int64_t>(1, 16 * p->Jt), 2048));
-    nb = std::min(nb, rows);
-    L.block_rows = fcs_ceil_div(rows, nb);
-    L.nblocks = fcs_ceil_div(rows, L.block_rows);
-    L.blocks_per_slab = L.nblocks;
+    const int64_t rb = std::min(nb, rows);
+    L.block_rows = fcs_ceil_div(rows, rb);
+    L.row_blocks = fcs_ceil_div(rows, L.block_rows);
+    const int64_t sb = std::max<int64_t>(1, std::min<int64_t>(nb / L.row_blocks, L.segs));
+    L.segs_per_block = (int)fcs_ceil_div(L.segs, sb);
+    L.seg_blocks = (int)fcs_ceil_div(L.segs, L.segs_per_block);
+    L.blocks_per_slab = L.row_blocks;
     return L;
 }
 
-// Kernels that use more than 64 KB of dynamic LDS opt in once.
+// Kernels that use more than 64 KB of dynamic LDS opt in to that amount
+// (static LDS of the kernel comes on top, within the 160 KB of a CU).
 template <typename K>
 void allow_lds(K kernel, size_t bytes) {
     if (bytes > 65536)
         (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)FCS_LDS_BYTES);
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+template <int DG, int NV>
+void launch_dense_nv(const DenseArgs &a, bool vec4, size_t lds, unsigned grid, hipStream_t s) {
+    if (vec4) {
+        allow_lds(dense_scatter_kernel<DG, NV, true>, lds);
+        hipLaunchKernelGGL((dense_scatter_kernel<DG, NV, true>), dim3(grid), dim3(DS_THREADS), lds, s, a);
+    } else {
+        allow_lds(dense_scatter_kernel<DG, NV, false>, lds);
+        hipLaunchKernelGGL((dense_scatter_kernel<DG, NV, false>), dim3(grid), dim3(DS_THREADS), lds, s, a);
+    }
 }
 
 template <int DG>
 void launch_dense(const DenseArgs &a, bool vec4, size_t lds, unsigned grid, hipStream_t s) {
-    if (vec4) {
-        allow_lds(dense_scatter_kernel<DG, true>, lds);
-        hipLaunchKernelGGL((dense_scatter_kernel<DG, true>), dim3(grid), dim3(DS_THREADS), lds, s, a);
-    } else {
-        allow_lds(dense_scatter_kernel<DG, false>, lds);
-        hipLaunchKernelGGL((dense_scatter_kernel<DG, false>), dim3(grid), dim3(DS_THREADS), lds, s, a);
+    switch (a.nrow_modes) {
+    case 0: launch_dense_nv<DG, 0>(a, vec4, lds, grid, s); break;
+    case 1: launch_dense_nv<DG, 1>(a, vec4, lds, grid, s); break;
+    case 2: launch_dense_nv<DG, 2>(a, vec4, lds, grid, s); break;
+    case 3: launch_dense_nv<DG, 3>(a, vec4, lds, grid, s); break;
+    case 4: launch_dense_nv<DG, 4>(a, vec4, lds, grid, s); break;
+    case 5: launch_dense_nv<DG, 5>(a, vec4, lds, grid, s); break;
+    case 6: launch_dense_nv<DG, 6>(a, vec4, lds, grid, s); break;
+    default: launch_dense_nv<DG, 7>(a, vec4, lds, grid, s); break;
     }
 }
 
 // ---------------------------------------------------------------------------
-// COO kernel: each workgroup holds the hash tables and the full J~ bins of DG
-// sketches in LDS and streams a contiguous range of entries.
+// COO kernel.  Each workgroup holds the hash tables of DG sketches and their
+// full J~ bins in LDS and streams a contiguous range of entries.  Bins are
+// 64-bit fixed-point integers (ds_add_u64): entries are rounded to 32-bit
+// integers at a per-workgroup power-of-two scale, so 2^31 additions cannot
+// overflow a bin and no period flush is needed; entries beyond the 32-bit
+// range, NaN and Inf take the float-atomic path.
 // ---------------------------------------------------------------------------
 constexpr int COO_THREADS = 1024;
+constexpr float QLIM32 = 2147483520.0f;   // largest float below 2^31
+constexpr int COO_TOP = 28;               // sample max maps into [2^27, 2^28)
 
 struct CooArgs {
     const int32_t *idx;
@@ -403,9 +546,10 @@ struct CooArgs {
 
 template <int DG>
 __global__ __launch_bounds__(COO_THREADS) void coo_scatter_kernel(CooArgs a) {
-    extern __shared__ uint32_t smem[];
-    uint32_t *tabs = smem;                                        // DG x sumI
-    float *bins = reinterpret_cast<float *>(smem + DG * a.sumI);  // DG x Jt
+    extern __shared__ unsigned long long smem64[];
+    unsigned long long *bins = smem64;                                        // DG x Jt
+    uint32_t *tabs = reinterpret_cast<uint32_t *>(smem64 + (size_t)DG * a.Jt);  // DG x sumI
+    __shared__ float wave_max[COO_THREADS / 64];
     const int64_t span = (int64_t)NXCD * a.ngroups;
     const int64_t super = blockIdx.x / span;
     const int64_t rem = blockIdx.x - super * span;
@@ -420,12 +564,32 @@ __global__ __launch_bounds__(COO_THREADS) void coo_scatter_kernel(CooArgs a) {
         const int d = k / sumI;
         tabs[k] = d < nd ? a.tab[(int64_t)(d0 + d) * a.sumI + (k - d * sumI)] : 0u;
     }
-    for (int k = threadIdx.x; k < DG * Jt; k += COO_THREADS) bins[k] = 0.f;
-    __syncthreads();
+    for (int k = threadIdx.x; k < DG * Jt; k += COO_THREADS) bins[k] = 0ull;
     const int64_t k0 = chunk * a.chunk;
     const int64_t k1 = min(k0 + a.chunk, a.nnz);
+    // scale from the largest magnitude among the chunk's first 16K entries
+    {
+        float m = 0.f;
+        for (int64_t k = k0 + threadIdx.x; k < min<int64_t>(k1, k0 + 16384); k += COO_THREADS)
+            m = fmaxf(m, fabsf(a.val[k]));
+        if (!(m <= 3.0e38f)) m = 0.f;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+        if ((threadIdx.x & 63) == 0) wave_max[threadIdx.x / 64] = m;
+    }
+    __syncthreads();
+    float M0 = 0.f;
+    for (int w = 0; w < COO_THREADS / 64; ++w) M0 = fmaxf(M0, wave_max[w]);
+    int F = COO_TOP - 1;
+    if (M0 > 0.f) F = COO_TOP - __builtin_amdgcn_frexp_expf(M0);
+    F = max(-100, min(100, F));
+    const float scale = ldexpf(1.0f, F);
+    const float inv = ldexpf(1.0f, -F);
+
     for (int64_t k = k0 + threadIdx.x; k < k1; k += COO_THREADS) {
         const float x = a.val[k];
+        const float xs = x * scale;
+        const bool ok = fabsf(xs) < QLIM32;
         int ix[FCS_MAX_ORDER];
         for (int n = 0; n < a.N; ++n) ix[n] = a.idx[(int64_t)n * a.nnz + k] + (int)a.off[n];
 #pragma unroll
@@ -438,17 +602,22 @@ __global__ __launch_bounds__(COO_THREADS) void coo_scatter_kernel(CooArgs a) {
                     H += (int)(p & FCS_H_MASK);
                     S ^= p & FCS_S_BIT;
                 }
-                __hip_atomic_fetch_add(&bins[d * Jt + H], __int_as_float(__float_as_int(x) ^ S),
-                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (ok) {
+                    const int q = cvt_rpi(__uint_as_float(__float_as_uint(xs) ^ S));
+                    __hip_atomic_fetch_add(&bins[d * Jt + H], (unsigned long long)(long long)q,
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                } else {
+                    unsafeAtomicAdd(a.out + (int64_t)(d0 + d) * a.Jt + H, __uint_as_float(__float_as_uint(x) ^ S));
+                }
             }
         }
     }
     __syncthreads();
     for (int k = threadIdx.x; k < nd * Jt; k += COO_THREADS) {
-        const float v = bins[k];
-        if (v != 0.f) {
+        const long long q = (long long)bins[k];
+        if (q != 0) {
             const int d = k / Jt;
-            unsafeAtomicAdd(a.out + (int64_t)(d0 + d) * a.Jt + (k - d * Jt), v);
+            unsafeAtomicAdd(a.out + (int64_t)(d0 + d) * a.Jt + (k - d * Jt), (float)((double)q * (double)inv));
         }
     }
 }
@@ -465,14 +634,14 @@ __global__ __launch_bounds__(256) void coo_scatter_global_kernel(CooArgs a) {
                 H += p & FCS_H_MASK;
                 S ^= p & FCS_S_BIT;
             }
-            unsafeAtomicAdd(a.out + (int64_t)d * a.Jt + H, __int_as_float(__float_as_int(x) ^ S));
+            unsafeAtomicAdd(a.out + (int64_t)d * a.Jt + H, __uint_as_float(__float_as_uint(x) ^ S));
         }
     }
 }
 
 int coo_dg(const fcs_plan *p) {
     const size_t budget = FCS_LDS_BYTES - 1024;
-    const size_t per_d = 4 * ((size_t)p->sumI + (size_t)p->Jt);
+    const size_t per_d = 8 * (size_t)p->Jt + 4 * (size_t)p->sumI;
     int dg = (int)std::min<size_t>(4, budget / per_d);
     return std::min(dg, p->D);
 }
@@ -496,7 +665,7 @@ extern "C" fcs_status fcs_sketch_dense(fcs_plan_t p, const float *T, float *out,
     a.out = out;
     a.tab = p->tab;
     for (int n = 0; n < FCS_MAX_ORDER; ++n) {
-        a.I[n] = n < p->N ? p->I[n] : 1;
+        a.I[n] = n < p->N ? (int32_t)p->I[n] : 1;
         a.off[n] = n < p->N ? p->off[n] : 0;
     }
     a.sumI = p->sumI;
@@ -518,15 +687,19 @@ extern "C" fcs_status fcs_sketch_dense(fcs_plan_t p, const float *T, float *out,
     a.slab_rows = L.slab_rows;
     a.block_rows = L.block_rows;
     a.blocks_per_slab = L.blocks_per_slab;
-    a.nblocks = L.nblocks;
-    a.W = L.W;
+    a.row_blocks = L.row_blocks;
+    a.W = (int)L.W;
     a.windowed = L.windowed ? 1 : 0;
-    a.segs = (int)fcs_ceil_div(a.I0, SEG);
+    a.nrow_modes = L.windowed ? p->N - 2 : p->N - 1;
+    a.segs = L.segs;
+    a.seg_blocks = L.seg_blocks;
+    a.segs_per_block = L.segs_per_block;
+    a.period = (int)std::max<int64_t>(1, ADD_BOUND / std::max(1, p->m0));
     const bool vec4 = (a.I0 % 4 == 0) && fcs_aligned(T, 16);
-    // whole groups of dg sketches, then one launch for the remainder
     const int full_groups = p->D / L.dg;
     const int tail = p->D - full_groups * L.dg;
-    const int64_t blocks_rounded = fcs_ceil_div(L.nblocks, NXCD) * NXCD;
+    const int64_t nblocks = L.row_blocks * L.seg_blocks;
+    const int64_t blocks_rounded = fcs_ceil_div(nblocks, NXCD) * NXCD;
     for (int pass = 0; pass < 2; ++pass) {
         const int dg = pass == 0 ? L.dg : tail;
         const int groups = pass == 0 ? full_groups : (tail ? 1 : 0);
@@ -535,7 +708,7 @@ extern "C" fcs_status fcs_sketch_dense(fcs_plan_t p, const float *T, float *out,
         a.d_first = pass == 0 ? 0 : full_groups * L.dg;
         const int64_t grid64 = blocks_rounded * groups;
         if (grid64 > INT32_MAX) FCS_FAIL(FCS_EUNSUPPORTED, "grid too large");
-        const size_t lds = (size_t)dg * (size_t)L.W * sizeof(float);
+        const size_t lds = (size_t)dg * (size_t)L.W * sizeof(uint32_t);
         switch (dg) {
         case 1: launch_dense<1>(a, vec4, lds, (unsigned)grid64, s); break;
         case 2: launch_dense<2>(a, vec4, lds, (unsigned)grid64, s); break;
@@ -583,7 +756,7 @@ extern "C" fcs_status fcs_sketch_coo(fcs_plan_t p, int64_t nnz, const int32_t *i
                                                              (int64_t)2048 / a.ngroups + 1));
     a.chunk = fcs_ceil_div(nnz, nchunks);
     a.nchunks = fcs_ceil_div(nnz, a.chunk);
-    const size_t lds = (size_t)dg * ((size_t)p->sumI + (size_t)p->Jt) * 4;
+    const size_t lds = (size_t)dg * (8 * (size_t)p->Jt + 4 * (size_t)p->sumI);
     const unsigned grid = (unsigned)(fcs_ceil_div(a.nchunks, NXCD) * NXCD * a.ngroups);
     allow_lds(coo_scatter_kernel<1>, lds);
     allow_lds(coo_scatter_kernel<2>, lds);

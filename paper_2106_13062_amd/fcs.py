@@ -12,7 +12,7 @@ import ctypes
 import numpy as np
 import torch
 
-from . import _lib as L
+from . import _lib as C
 
 _I64 = ctypes.c_int64
 
@@ -43,7 +43,7 @@ class Plan:
     hash lengths J, hash pairs drawn from ``seed`` (see include/fcs.h)."""
 
     def __init__(self, I, J, D: int, seed: int, L: int = 0, device=None, stream=None):
-        self.lib = L.load()
+        self.lib = C.load()
         self.I = tuple(int(i) for i in I)
         self.J = tuple(int(j) for j in J)
         self.N = len(self.I)
@@ -51,19 +51,19 @@ class Plan:
         self.seed = int(seed) & ((1 << 64) - 1)
         Ia = (_I64 * self.N)(*self.I)
         Ja = (_I64 * self.N)(*self.J)
-        desc = L.PlanDesc(self.N, Ia, Ja, self.D, self.seed, int(L))
+        desc = C.PlanDesc(self.N, Ia, Ja, self.D, self.seed, int(L))
         h = ctypes.c_void_p()
-        L.check(self.lib.fcs_plan_create(ctypes.byref(desc), ctypes.byref(h)))
+        C.check(self.lib.fcs_plan_create(ctypes.byref(desc), ctypes.byref(h)))
         self._h = h
         Jt, Lt, Pt, Qt = _I64(), _I64(), _I64(), ctypes.c_int32()
-        L.check(self.lib.fcs_plan_info(h, ctypes.byref(Jt), ctypes.byref(Lt), ctypes.byref(Pt),
+        C.check(self.lib.fcs_plan_info(h, ctypes.byref(Jt), ctypes.byref(Lt), ctypes.byref(Pt),
                                        ctypes.byref(Qt)))
         self.Jt, self.L, self.P, self.Q = Jt.value, Lt.value, Pt.value, Qt.value
         self.spec_len = int(self.lib.fcs_plan_spec_len(h))
         self.device = torch.device("cuda") if device is None else torch.device(device)
         nbytes = int(self.lib.fcs_plan_table_bytes(h))
         self.tables = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
-        L.check(self.lib.fcs_plan_bind(h, _ptr(self.tables), _stream(stream)))
+        C.check(self.lib.fcs_plan_bind(h, _ptr(self.tables), _stream(stream)))
 
     # ------------------------------------------------------------------ utils
     def close(self):
@@ -88,7 +88,7 @@ class Plan:
     def export(self, d: int, n: int, stream=None):
         h = np.empty(self.I[n], dtype=np.int32)
         s = np.empty(self.I[n], dtype=np.int8)
-        L.check(self.lib.fcs_plan_export(self._h, d, n, h.ctypes.data_as(ctypes.c_void_p),
+        C.check(self.lib.fcs_plan_export(self._h, d, n, h.ctypes.data_as(ctypes.c_void_p),
                                          s.ctypes.data_as(ctypes.c_void_p), _stream(stream)))
         return h, s
 
@@ -105,8 +105,8 @@ class Plan:
             raise ValueError("T has the wrong number of entries")
         out = torch.empty((self.D, self.Jt), dtype=torch.float32, device=self.device) if out is None else out
         _need(out, torch.float32, "out")
-        ws, nb = self._ws(ws, L.OP_DENSE)
-        L.check(self.lib.fcs_sketch_dense(self._h, _ptr(T), _ptr(out), _ptr(ws), nb, _stream(stream)))
+        ws, nb = self._ws(ws, C.OP_DENSE)
+        C.check(self.lib.fcs_sketch_dense(self._h, _ptr(T), _ptr(out), _ptr(ws), nb, _stream(stream)))
         return out
 
     def sketch_coo(self, idx: torch.Tensor, val: torch.Tensor, out=None, ws=None, stream=None):
@@ -118,8 +118,8 @@ class Plan:
             raise ValueError("idx must be N x nnz")
         out = torch.empty((self.D, self.Jt), dtype=torch.float32, device=self.device) if out is None else out
         _need(out, torch.float32, "out")
-        ws, nb = self._ws(ws, L.OP_COO)
-        L.check(self.lib.fcs_sketch_coo(self._h, nnz, _ptr(idx), _ptr(val), _ptr(out), _ptr(ws), nb,
+        ws, nb = self._ws(ws, C.OP_COO)
+        C.check(self.lib.fcs_sketch_coo(self._h, nnz, _ptr(idx), _ptr(val), _ptr(out), _ptr(ws), nb,
                                         _stream(stream)))
         return out
 
@@ -141,8 +141,8 @@ class Plan:
         if want_spec and spec is None:
             spec = torch.empty((self.D, self.spec_len, 2), dtype=torch.float32, device=self.device)
         ptrs = (ctypes.c_void_p * self.N)(*[u.data_ptr() for u in U])
-        ws, nb = self._ws(ws, L.OP_CP, R=R)
-        L.check(self.lib.fcs_sketch_cp(self._h, R, ptrs, _ptr(lam), _ptr(out), _ptr(spec), _ptr(ws), nb,
+        ws, nb = self._ws(ws, C.OP_CP, R=R)
+        C.check(self.lib.fcs_sketch_cp(self._h, R, ptrs, _ptr(lam), _ptr(out), _ptr(spec), _ptr(ws), nb,
                                        _stream(stream)))
         return out, spec
 
@@ -150,8 +150,8 @@ class Plan:
         _need(y, torch.float32, "y")
         spec = torch.empty((self.D, self.spec_len, 2), dtype=torch.float32, device=self.device) \
             if spec is None else spec
-        ws, nb = self._ws(ws, L.OP_SPECTRUM)
-        L.check(self.lib.fcs_sketch_spectrum(self._h, _ptr(y), _ptr(spec), _ptr(ws), nb, _stream(stream)))
+        ws, nb = self._ws(ws, C.OP_SPECTRUM)
+        C.check(self.lib.fcs_sketch_spectrum(self._h, _ptr(y), _ptr(spec), _ptr(ws), nb, _stream(stream)))
         return spec
 
     # ----------------------------------------------------------- contractions
@@ -160,8 +160,8 @@ class Plan:
         _need(b, torch.float32, "b")
         med = torch.empty(1, dtype=torch.float64, device=self.device)
         per_d = torch.empty(self.D, dtype=torch.float64, device=self.device)
-        ws, nb = self._ws(ws, L.OP_INNER)
-        L.check(self.lib.fcs_contract_inner(self._h, _ptr(a), _ptr(b), _ptr(med), _ptr(per_d), _ptr(ws), nb,
+        ws, nb = self._ws(ws, C.OP_INNER)
+        C.check(self.lib.fcs_contract_inner(self._h, _ptr(a), _ptr(b), _ptr(med), _ptr(per_d), _ptr(ws), nb,
                                             _stream(stream)))
         return med, per_d
 
@@ -184,7 +184,7 @@ class Plan:
         Pn = 0 if Pn is None else Pn
         out = torch.empty((Pn, self.I[free_mode]), dtype=torch.float64, device=self.device) \
             if out is None else out
-        ws, nb = self._ws(ws, L.OP_FREE_MODE, P=Pn)
-        L.check(self.lib.fcs_contract_free_mode(self._h, _ptr(spec), int(free_mode), Pn, ptrs, _ptr(out),
+        ws, nb = self._ws(ws, C.OP_FREE_MODE, P=Pn)
+        C.check(self.lib.fcs_contract_free_mode(self._h, _ptr(spec), int(free_mode), Pn, ptrs, _ptr(out),
                                                 _ptr(ws), nb, _stream(stream)))
         return out
