@@ -93,6 +93,8 @@ __device__ __forceinline__ int cvt_rpi(float x) {
     return r;
 }
 
+__device__ __forceinline__ int64_t fcs_ceil_div_dev(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
 __device__ inline void dense_block_map(const DenseArgs &a, int64_t bid, int64_t &blk, int &grp) {
     const int64_t span = (int64_t)NXCD * a.ngroups;
     const int64_t super = bid / span;
@@ -100,58 +102,6 @@ __device__ inline void dense_block_map(const DenseArgs &a, int64_t bid, int64_t 
     grp = (int)(rem / NXCD);
     blk = super * NXCD + (rem % NXCD);
 }
-
-// Row-mode state of one wave: the mixed-radix index (i_1, ..., i_NV) of its
-// current row and the table pointers of those modes for every sketch.
-template <int DG, int NV>
-struct RowWalk {
-    int idx[NV > 0 ? NV : 1];
-    const uint32_t *tp[NV > 0 ? NV : 1][DG];
-
-    __device__ __forceinline__ void init(const DenseArgs &a, int d0, int64_t r) {
-#pragma unroll
-        for (int n = 0; n < NV; ++n) {
-            idx[n] = (int)(r % a.I[n + 1]);
-            r /= a.I[n + 1];
-#pragma unroll
-            for (int d = 0; d < DG; ++d) tp[n][d] = a.tab + (int64_t)(d0 + d) * a.sumI + a.off[n + 1];
-        }
-    }
-    __device__ __forceinline__ void advance(const DenseArgs &a, int step) {
-        int carry = step;
-#pragma unroll
-        for (int n = 0; n < NV; ++n) {
-            if (carry) {
-                const int In = a.I[n + 1];
-                const int t = idx[n] + carry;
-                if (t < In) {
-                    idx[n] = t;
-                    carry = 0;
-                } else {
-                    idx[n] = t % In;
-                    carry = t / In;
-                }
-            }
-        }
-    }
-    // row offset (bytes) and row sign of every sketch of the group
-    __device__ __forceinline__ void hash(uint32_t (&C)[DG], uint32_t (&R)[DG]) const {
-#pragma unroll
-        for (int d = 0; d < DG; ++d) {
-            C[d] = 0;
-            R[d] = 0;
-        }
-#pragma unroll
-        for (int n = 0; n < NV; ++n) {
-#pragma unroll
-            for (int d = 0; d < DG; ++d) {
-                const uint32_t w = tp[n][d][idx[n]];
-                C[d] += (w & FCS_H_MASK) * 4u;
-                R[d] ^= w & FCS_S_BIT;
-            }
-        }
-    }
-};
 
 template <bool VEC4, bool FULL>
 __device__ __forceinline__ void load_seg(const float *row, int lane, const bool (&valid)[4], float (&x)[4]) {
@@ -164,14 +114,14 @@ __device__ __forceinline__ void load_seg(const float *row, int lane, const bool 
     }
 }
 
-// Out-of-range or non-finite entries: float atomics into the HBM sketch, with
-// every sign including the slab's last-mode sign.
+// Out-of-range or non-finite entries of one row segment: float atomics into
+// the HBM sketch, with every sign including the slab's last-mode sign.
 template <int DG, bool CHECK>
 __device__ __forceinline__ void scatter_slow(const DenseArgs &a, const float (&x)[4], float scale, int d0,
-                                                       const uint32_t (&A)[DG][4], const uint32_t (&M)[DG][4],
-                                                       const bool (&valid)[4], const uint32_t (&C)[DG],
-                                                       const uint32_t (&R)[DG], const int (&base)[DG],
-                                                       const uint32_t (&wsign)[DG]) {
+                                             const uint32_t (&A)[DG][4], const uint32_t (&M)[DG][4],
+                                             const bool (&valid)[4], const uint32_t (&C)[DG],
+                                             const uint32_t (&R)[DG], const int (&base)[DG],
+                                             const uint32_t (&wsign)[DG]) {
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
         const float xe = x[e];
@@ -188,6 +138,8 @@ __device__ __forceinline__ void scatter_slow(const DenseArgs &a, const float (&x
 }
 
 // Add one row segment (4 values per lane) to the DG fixed-point windows.
+// The in-range test is per element; a wave with any out-of-range element
+// in the row takes the slow path for those elements (uniform branch).
 template <int DG, bool CHECK>
 __device__ __forceinline__ void scatter_seg(const DenseArgs &a, uint32_t *qbins, const float (&x)[4], float scale,
                                             int d0, const uint32_t (&A)[DG][4], const uint32_t (&M)[DG][4],
@@ -201,7 +153,11 @@ __device__ __forceinline__ void scatter_seg(const DenseArgs &a, uint32_t *qbins,
         xs[e] = x[e] * scale;
         const bool ok = fabsf(xs[e]) < QLIM;     // false for NaN / Inf too
         slow |= (!ok) && (!CHECK || valid[e]);
-        xs[e] = ok ? xs[e] : 0.f;
+    }
+    if (__builtin_expect(__builtin_amdgcn_ballot_w64(slow) != 0, 0)) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) xs[e] = fabsf(xs[e]) < QLIM ? xs[e] : 0.f;
+        scatter_slow<DG, CHECK>(a, x, scale, d0, A, M, valid, C, R, base, wsign);
     }
 #pragma unroll
     for (int d = 0; d < DG; ++d) {
@@ -214,51 +170,127 @@ __device__ __forceinline__ void scatter_seg(const DenseArgs &a, uint32_t *qbins,
             }
         }
     }
-    if (__builtin_expect(slow, 0)) scatter_slow<DG, CHECK>(a, x, scale, d0, A, M, valid, C, R, base, wsign);
 }
 
-// Rows [r_first, r1) with stride wps of one segment; the next row's hash words
-// and values are in flight while the current row is scattered.
-template <int DG, int NV, bool VEC4, bool FULL>
-__device__ __forceinline__ void segment_rows(const DenseArgs &a, uint32_t *qbins, float scale, int d0, int seg,
-                                             int lane, int64_t r_first, int64_t r1, int wps,
-                                             const uint32_t (&A)[DG][4], const uint32_t (&M)[DG][4],
-                                             const bool (&valid)[4], const int (&base)[DG],
-                                             const uint32_t (&wsign)[DG]) {
-    if (r_first >= r1) return;
-    RowWalk<DG, NV> walk;
-    walk.init(a, d0, r_first);
-    const float *Tseg = a.T + (int64_t)seg * SEG;
-    uint32_t C[DG], R[DG];
-    float x[4];
-    walk.hash(C, R);
-    load_seg<VEC4, FULL>(Tseg + r_first * a.I0, lane, valid, x);
-    for (int64_t r = r_first; r < r1; r += wps) {
-        const int64_t rn = r + wps;
-        uint32_t Cn[DG], Rn[DG];
-        float xn[4];
-        if (rn < r1) {
-            walk.advance(a, wps);
-            walk.hash(Cn, Rn);
-            load_seg<VEC4, FULL>(Tseg + rn * a.I0, lane, valid, xn);
-        }
-        scatter_seg<DG, !FULL>(a, qbins, x, scale, d0, A, M, valid, C, R, base, wsign);
-        if (rn < r1) {
+// Row offsets and signs of 64 consecutive rows of a wave, one row per lane:
+// lane j holds, for every sketch of the group, (byte offset of row
+// rb + j * wps in the window) | (row sign bit).  Rows are fetched 64 at a
+// time and broadcast with v_readlane, so the hot loop issues no per-row
+// table loads.  The chunk's first row rb is decoded once (uniform); each lane
+// adds its offset j * wps < 1024 with 32-bit carries.
+template <int DG, int NV>
+__device__ __forceinline__ void row_words(const DenseArgs &a, int d0, int64_t rb, int lane, int wps, bool live,
+                                          uint32_t (&CR)[DG]) {
+    int idx[NV > 0 ? NV : 1];
+    {
+        int64_t r = rb;
+        uint32_t carry = (uint32_t)(lane * wps);
 #pragma unroll
-            for (int d = 0; d < DG; ++d) {
-                C[d] = Cn[d];
-                R[d] = Rn[d];
+        for (int n = 0; n < NV; ++n) {
+            const uint32_t In = (uint32_t)a.I[n + 1];
+            const uint32_t b = (uint32_t)(r % In);
+            r /= In;
+            const uint32_t t = b + carry;
+            if (t < In) {
+                idx[n] = (int)t;
+                carry = 0;
+            } else {
+                idx[n] = (int)(t % In);
+                carry = t / In;
             }
-#pragma unroll
-            for (int e = 0; e < 4; ++e) x[e] = xn[e];
         }
+    }
+#pragma unroll
+    for (int d = 0; d < DG; ++d) {
+        uint32_t c = 0, sg = 0;
+#pragma unroll
+        for (int n = 0; n < NV; ++n) {
+            const uint32_t w = live ? a.tab[(int64_t)(d0 + d) * a.sumI + a.off[n + 1] + idx[n]] : 0u;
+            c += (w & FCS_H_MASK) * 4u;
+            sg ^= w & FCS_S_BIT;
+        }
+        CR[d] = c | sg;
     }
 }
 
-template <int DG, int NV, bool VEC4>
+// One wave's rows r_first + k * wps (k < nk) of one column segment, in flush
+// periods of pk rows.  Two row loads are in flight (ping-pong buffers) and
+// stay in flight across the period barriers.  Every wave of the workgroup
+// calls this with the same period count so all reach every barrier.
+template <int DG, int NV, bool VEC4, bool FULL>
+__device__ __forceinline__ void wave_rows(const DenseArgs &a, uint32_t *qbins, float (&acc)[MAXACC], float scale,
+                                          float inv, int d0, int seg, int lane, bool active, int64_t r_first,
+                                          int64_t nk, int wps, int64_t pk, int64_t nperiods, const int (&base)[DG],
+                                          const uint32_t (&wsign)[DG]) {
+    const int W = a.W;
+    uint32_t A[DG][4], M[DG][4];
+    bool valid[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int64_t col = (int64_t)seg * SEG + lane * 4 + e;
+        valid[e] = active && col < a.I0;
+#pragma unroll
+        for (int d = 0; d < DG; ++d) {
+            const uint32_t p = valid[e] ? a.tab[(int64_t)(d0 + d) * a.sumI + col] : 0u;
+            A[d][e] = (uint32_t)((d * W + (int)(p & FCS_H_MASK)) * 4);
+            M[d][e] = p & FCS_S_BIT;
+        }
+    }
+    const float *Tseg = a.T + (int64_t)seg * SEG;
+    const int64_t rstride = (int64_t)wps * a.I0;
+    float b0[4], b1[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        b0[e] = 0.f;
+        b1[e] = 0.f;
+    }
+    if (active && nk > 0) load_seg<VEC4, FULL>(Tseg + r_first * a.I0, lane, valid, b0);
+    if (active && nk > 1) load_seg<VEC4, FULL>(Tseg + r_first * a.I0 + rstride, lane, valid, b1);
+    uint32_t CR[DG];
+    row_words<DG, NV>(a, d0, r_first, lane, wps, active && lane < nk, CR);
+
+    for (int64_t p = 0; p < nperiods; ++p) {
+        const int64_t kb = p * pk;
+        const int64_t ke = min(kb + pk, active ? nk : (int64_t)0);
+        for (int64_t k = kb; k < ke; ++k) {
+            if ((k & 63) == 0 && k > 0) row_words<DG, NV>(a, d0, r_first + k * wps, lane, wps, k + lane < nk, CR);
+            uint32_t C[DG], R[DG];
+#pragma unroll
+            for (int d = 0; d < DG; ++d) {
+                const uint32_t w = __builtin_amdgcn_readlane(CR[d], (int)(k & 63));
+                C[d] = w & FCS_H_MASK;
+                R[d] = w & FCS_S_BIT;
+            }
+            float x[4];
+            if (k & 1) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) x[e] = b1[e];
+                if (k + 2 < nk) load_seg<VEC4, FULL>(Tseg + (r_first * a.I0 + (k + 2) * rstride), lane, valid, b1);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) x[e] = b0[e];
+                if (k + 2 < nk) load_seg<VEC4, FULL>(Tseg + (r_first * a.I0 + (k + 2) * rstride), lane, valid, b0);
+            }
+            scatter_seg<DG, !FULL>(a, qbins, x, scale, d0, A, M, valid, C, R, base, wsign);
+        }
+        __syncthreads();
+        // period flush: integer bins -> float register accumulators (exact
+        // scaling by 2^-F), bins back to zero
+#pragma unroll
+        for (int m = 0; m < MAXACC; ++m) {
+            const int kq = threadIdx.x + m * DS_THREADS;
+            if (kq < DG * W) {
+                acc[m] += (float)(int)qbins[kq] * inv;
+                qbins[kq] = 0u;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <int DG, int NV, bool VEC4, bool FULL>
 __global__ __launch_bounds__(DS_THREADS) void dense_scatter_kernel(DenseArgs a) {
     extern __shared__ uint32_t qbins[];     // DG x W fixed-point bins
-    __shared__ float wave_max[DS_WAVES];
     int64_t blk;
     int grp;
     dense_block_map(a, blockIdx.x, blk, grp);
@@ -267,7 +299,7 @@ __global__ __launch_bounds__(DS_THREADS) void dense_scatter_kernel(DenseArgs a) 
     const int sblk = (int)(blk - rblk * a.seg_blocks);
     const int d0 = a.d_first + grp * DG;
 
-    // rows and column segments of this block
+    // rows and column segments of this block (at most 16 segments)
     int64_t r0, r1;
     if (a.windowed) {
         const int64_t slab = rblk / a.blocks_per_slab;
@@ -298,13 +330,12 @@ __global__ __launch_bounds__(DS_THREADS) void dense_scatter_kernel(DenseArgs a) 
     }
 
     const int W = a.W;
-    for (int k = threadIdx.x; k < DG * W; k += DS_THREADS) qbins[k] = 0u;
-
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
     const int lane = threadIdx.x % 64;
 
     // scale: largest magnitude among up to 16 leading rows (first 4096
-    // columns of the block's segments), mapped into [2^19, 2^20)
+    // columns of the block's segments), mapped into [2^19, 2^20); the wave
+    // maxima are exchanged through the (not yet used) bin memory
     {
         const int64_t nrows = r1 - r0;
         const int64_t r = r0 + (wave % nrows);
@@ -316,12 +347,15 @@ __global__ __launch_bounds__(DS_THREADS) void dense_scatter_kernel(DenseArgs a) 
         if (!(m <= 3.0e38f)) m = 0.f;
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
-        if (lane == 0) wave_max[wave] = m;
+        if (lane == 0) qbins[wave] = __float_as_uint(m);
     }
     __syncthreads();
     float M0 = 0.f;
 #pragma unroll
-    for (int w = 0; w < DS_WAVES; ++w) M0 = fmaxf(M0, wave_max[w]);
+    for (int w = 0; w < DS_WAVES; ++w) M0 = fmaxf(M0, __uint_as_float(qbins[w]));
+    __syncthreads();
+    for (int k = threadIdx.x; k < DG * W; k += DS_THREADS) qbins[k] = 0u;
+    __syncthreads();
     int F = SCALE_TOP - 1;
     if (M0 > 0.f) F = SCALE_TOP - __builtin_amdgcn_frexp_expf(M0);
     F = max(-100, min(100, F));
@@ -332,45 +366,19 @@ __global__ __launch_bounds__(DS_THREADS) void dense_scatter_kernel(DenseArgs a) 
 #pragma unroll
     for (int m = 0; m < MAXACC; ++m) acc[m] = 0.f;
 
+    // each wave owns at most one (segment, row lane) of the block
     const int wps = max(1, DS_WAVES / nseg);             // waves per segment
-    for (int64_t p0 = r0; p0 < r1; p0 += a.period) {
-        const int64_t p1 = min<int64_t>(p0 + a.period, r1);
-        for (int sidx = wave; sidx < nseg * wps; sidx += DS_WAVES) {
-            const int seg = s0 + sidx % nseg;
-            const int rl = sidx / nseg;
-            uint32_t A[DG][4], M[DG][4];
-            bool valid[4];
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int64_t col = (int64_t)seg * SEG + lane * 4 + e;
-                valid[e] = col < a.I0;
-#pragma unroll
-                for (int d = 0; d < DG; ++d) {
-                    const uint32_t p = valid[e] ? a.tab[(int64_t)(d0 + d) * a.sumI + col] : 0u;
-                    A[d][e] = (uint32_t)((d * W + (int)(p & FCS_H_MASK)) * 4);
-                    M[d][e] = p & FCS_S_BIT;
-                }
-            }
-            if ((int64_t)(seg + 1) * SEG <= a.I0)
-                segment_rows<DG, NV, VEC4, true>(a, qbins, scale, d0, seg, lane, p0 + rl, p1, wps, A, M, valid,
-                                                 base, wsign);
-            else
-                segment_rows<DG, NV, VEC4, false>(a, qbins, scale, d0, seg, lane, p0 + rl, p1, wps, A, M, valid,
-                                                  base, wsign);
-        }
-        __syncthreads();
-        // period flush: integer bins -> float register accumulators (exact
-        // scaling by 2^-F), bins back to zero
-#pragma unroll
-        for (int m = 0; m < MAXACC; ++m) {
-            const int k = threadIdx.x + m * DS_THREADS;
-            if (k < DG * W) {
-                acc[m] += (float)(int)qbins[k] * inv;
-                qbins[k] = 0u;
-            }
-        }
-        __syncthreads();
-    }
+    const int64_t nrows = r1 - r0;
+    const bool active = wave < nseg * wps;
+    const int seg = s0 + (active ? wave % nseg : 0);
+    const int rl = active ? wave / nseg : 0;
+    const int64_t nk = (active && rl < nrows) ? (nrows - rl + wps - 1) / wps : 0;
+    const int64_t pk = max<int64_t>(1, a.period / wps);
+    const int64_t nperiods = (fcs_ceil_div_dev(nrows, wps) + pk - 1) / pk;
+    // FULL kernels are launched only when every segment is complete
+    wave_rows<DG, NV, VEC4, FULL>(a, qbins, acc, scale, inv, d0, seg, lane, active, r0 + rl, nk, wps, pk, nperiods,
+                                  base, wsign);
+
     // add the window to the HBM sketch, with the slab's last-mode sign
 #pragma unroll
     for (int m = 0; m < MAXACC; ++m) {
@@ -458,8 +466,8 @@ DenseLaunch plan_dense(const fcs_plan *p) {
                 L.block_rows = fcs_ceil_div(slab_rows, bps);
                 L.blocks_per_slab = fcs_ceil_div(slab_rows, L.block_rows);
                 L.row_blocks = L.blocks_per_slab * p->I[p->N - 1];
-                L.seg_blocks = 1;
-                L.segs_per_block = L.segs;
+                L.segs_per_block = std::min(L.segs, DS_WAVES);
+                L.seg_blocks = (int)fcs_ceil_div(L.segs, L.segs_per_block);
                 return L;
             }
         }
@@ -478,7 +486,7 @@ DenseLaunch plan_dense(const fcs_plan *p) {
     L.block_rows = fcs_ceil_div(rows, rb);
     L.row_blocks = fcs_ceil_div(rows, L.block_rows);
     const int64_t sb = std::max<int64_t>(1, std::min<int64_t>(nb / L.row_blocks, L.segs));
-    L.segs_per_block = (int)fcs_ceil_div(L.segs, sb);
+    L.segs_per_block = std::min<int>((int)fcs_ceil_div(L.segs, sb), DS_WAVES);
     L.seg_blocks = (int)fcs_ceil_div(L.segs, L.segs_per_block);
     L.blocks_per_slab = L.row_blocks;
     return L;
@@ -495,12 +503,13 @@ void allow_lds(K kernel, size_t bytes) {
 
 template <int DG, int NV>
 void launch_dense_nv(const DenseArgs &a, bool vec4, size_t lds, unsigned grid, hipStream_t s) {
-    if (vec4) {
-        allow_lds(dense_scatter_kernel<DG, NV, true>, lds);
-        hipLaunchKernelGGL((dense_scatter_kernel<DG, NV, true>), dim3(grid), dim3(DS_THREADS), lds, s, a);
+    if (vec4 && a.I0 % SEG == 0) {
+        // every segment complete: the fast instance
+        allow_lds(dense_scatter_kernel<DG, NV, true, true>, lds);
+        hipLaunchKernelGGL((dense_scatter_kernel<DG, NV, true, true>), dim3(grid), dim3(DS_THREADS), lds, s, a);
     } else {
-        allow_lds(dense_scatter_kernel<DG, NV, false>, lds);
-        hipLaunchKernelGGL((dense_scatter_kernel<DG, NV, false>), dim3(grid), dim3(DS_THREADS), lds, s, a);
+        allow_lds(dense_scatter_kernel<DG, NV, false, false>, lds);
+        hipLaunchKernelGGL((dense_scatter_kernel<DG, NV, false, false>), dim3(grid), dim3(DS_THREADS), lds, s, a);
     }
 }
 
