@@ -1,20 +1,527 @@
-// CP sketch, spectra and T(I, u, v) contractions (Sections 3.1 and 4.1).
+// CP sketch, sketch spectra and T(I, u, v) contractions (Sections 3.1 and
+// 4.1 of the paper).
+//
+// Transform layout.  The plan's transform length is L = Q * P with P a power
+// of two held in LDS.  The L-point DFT of a sequence x supported on [0, M) is
+// split into Q interleaved slices: X[Q k + q] = DFT_P(w_q)[k] with
+// w_q[m] = sum_t x[m + tP] exp(-2 pi i q (m + tP) / L)  (a twisted fold), so
+// every slice is one P-point FFT in LDS.  The spectrum of a real sequence is
+// conjugate-symmetric, so only slices q = 0..floor(Q/2) are formed; the
+// inverse combines them as
+//   y[m] = (1/L) sum_q c_q Re( exp(+2 pi i q m / L) Z_q[m mod P] ),
+// Z_q the unnormalised inverse P-point DFT of slice q, c_q = 1 for q = 0 and
+// (Q even) q = Q/2, else 2.  Any L >= J~ gives the linear convolution of the
+// paper's J~-point zero-padded transforms, truncated to J~.
+//
+// Count sketches inside the transforms are gathers, not scatters: the plan
+// holds the inverse hash lists (indices grouped by h_n), so the thread that
+// owns position m of a slice sums the entries of the buckets that fold onto
+// m.  No LDS atomics are needed (float LDS atomics are slow on gfx950).
 #include "fcs_internal.h"
 
-size_t fcs_ws_cp(const fcs_plan *, int64_t) { return 256; }
-size_t fcs_ws_free_mode(const fcs_plan *, int64_t) { return 256; }
+#include <algorithm>
+
+#include "fft.h"
+#include "median.h"
+
+using namespace fcsfft;
+
+namespace {
+
+struct SliceArgs {
+    const float2 *twP;
+    const float2 *twL;
+    int L, P, Q, Qh;
+};
+
+// Slice q of the DFT of one mode's count sketch CS_n(u): builds w_q in LDS
+// (natural order, padded).  u is the factor column (I_n floats), the inverse
+// lists give the buckets of h_n.  Each thread writes its own positions.
+template <int P>
+__device__ __forceinline__ void build_cs_slice(float2 *lds, const float *__restrict__ u,
+                                               const int32_t *__restrict__ off,
+                                               const int32_t *__restrict__ ent, int Jn, int q,
+                                               const SliceArgs &s, float scale) {
+    constexpr int T = Shape<P>::T;
+    for (int m = tid_opaque(); m < P; m += T) {
+        float2 acc = make_float2(0.f, 0.f);
+        for (int j = m; j < Jn; j += P) {
+            float y = 0.f;
+            const int b0 = off[j], b1 = off[j + 1];
+            for (int k = b0; k < b1; ++k) {
+                const uint32_t e = (uint32_t)ent[k];
+                const float v = u[e & FCS_H_MASK];
+                y += __uint_as_float(__float_as_uint(v) ^ (e & FCS_S_BIT));
+            }
+            if (q == 0) {
+                acc.x += y;
+            } else {
+                const float2 w = s.twL[(int)(((int64_t)q * j) % s.L)];
+                acc.x += y * w.x;
+                acc.y += y * w.y;
+            }
+        }
+        lds[pad(m)] = make_float2(acc.x * scale, acc.y * scale);
+    }
+}
+
+// Slice q of the DFT of a dense real sequence y[0..M): w_q in LDS.
+template <int P>
+__device__ __forceinline__ void build_seq_slice(float2 *lds, const float *__restrict__ y, int M, int q,
+                                                const SliceArgs &s) {
+    constexpr int T = Shape<P>::T;
+    for (int m = tid_opaque(); m < P; m += T) {
+        float2 acc = make_float2(0.f, 0.f);
+        for (int j = m; j < M; j += P) {
+            const float v = y[j];
+            if (q == 0) {
+                acc.x += v;
+            } else {
+                const float2 w = s.twL[(int)(((int64_t)q * j) % s.L)];
+                acc.x += v * w.x;
+                acc.y += v * w.y;
+            }
+        }
+        lds[pad(m)] = acc;
+    }
+}
+
+// Real part of the slice-q term of the inverse at position m:
+// c_q Re(exp(+2 pi i q m / L) Z) / L.
+__device__ __forceinline__ float inv_term(const SliceArgs &s, int q, int64_t m, float2 Z) {
+    const float cq = (q == 0 || (2 * q == s.Q)) ? 1.f : 2.f;
+    if (q == 0) return cq * Z.x / (float)s.L;
+    const float2 w = s.twL[(int)(((int64_t)q * m) % s.L)];   // exp(-2 pi i q m / L)
+    return cq * (w.x * Z.x + w.y * Z.y) / (float)s.L;         // Re(conj(w) Z)
+}
+
+// ---------------------------------------------------------------------------
+// CP sketch, forward part: one workgroup per (sketch d, slice q, rank chunk);
+// for every rank r of the chunk the N mode spectra of slice q are formed in
+// LDS, multiplied in registers, weighted by lambda_r and summed; the chunk's
+// partial spectrum goes to the workspace.
+// ---------------------------------------------------------------------------
+struct CpArgs {
+    const float *U[FCS_MAX_ORDER];
+    const float *lambda;
+    int I[FCS_MAX_ORDER];
+    int J[FCS_MAX_ORDER];
+    const int32_t *inv;
+    int64_t ioff[FCS_MAX_ORDER];
+    int64_t iblock;
+    int N, D, R, nchunks, rchunk;
+    SliceArgs s;
+    float2 *partial;        // [D][Qh][nchunks][P]
+};
+
+template <int P>
+__global__ __launch_bounds__(Shape<P>::T) void cp_forward_kernel(CpArgs a) {
+    extern __shared__ float2 lds[];
+    constexpr int E = Shape<P>::E;
+    constexpr int T = Shape<P>::T;
+    const int tile = blockIdx.x;
+    const int chunk = tile % a.nchunks;
+    const int q = (tile / a.nchunks) % a.s.Qh;
+    const int d = tile / (a.nchunks * a.s.Qh);
+    const int r0 = chunk * a.rchunk;
+    const int r1 = min(a.R, r0 + a.rchunk);
+    float2 acc[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) acc[e] = make_float2(0.f, 0.f);
+    const int32_t *invd = a.inv + (int64_t)d * a.iblock;
+    for (int r = r0; r < r1; ++r) {
+        float2 prod[E];
+        const float lam = a.lambda ? a.lambda[r] : 1.0f;
+        for (int n = 0; n < a.N; ++n) {
+            const int32_t *off = invd + a.ioff[n];
+            build_cs_slice<P>(lds, a.U[n] + (int64_t)r * a.I[n], off, off + a.J[n] + 1, a.J[n], q, a.s,
+                              n == 0 ? lam : 1.0f);
+            __syncthreads();
+            float2 v[E];
+            forward<P>(lds, a.s.twP, v);
+#pragma unroll
+            for (int e = 0; e < E; ++e) prod[e] = (n == 0) ? v[e] : cmul(prod[e], v[e]);
+        }
+#pragma unroll
+        for (int e = 0; e < E; ++e) acc[e] = cadd(acc[e], prod[e]);
+    }
+    float2 *dst = a.partial + (((int64_t)d * a.s.Qh + q) * a.nchunks + chunk) * P;
+#pragma unroll
+    for (int e = 0; e < E; ++e) dst[threadIdx.x + e * T] = acc[e];
+}
+
+// ---------------------------------------------------------------------------
+// Inverse part: one workgroup per sketch; sums the chunk partials of every
+// slice (fixed order), optionally stores the spectrum, inverts the slices
+// and accumulates y[0..J~) in HBM (each thread owns fixed positions).
+// ---------------------------------------------------------------------------
+struct FinArgs {
+    const float2 *partial;
+    int nchunks;
+    SliceArgs s;
+    float *out;             // D x Jt or null
+    float2 *spec;           // D x (Qh * P) or null
+    int64_t Jt;
+};
+
+template <int P>
+__global__ __launch_bounds__(Shape<P>::T) void cp_finalize_kernel(FinArgs a) {
+    extern __shared__ float2 lds[];
+    constexpr int E = Shape<P>::E;
+    constexpr int T = Shape<P>::T;
+    const int d = blockIdx.x;
+    for (int q = 0; q < a.s.Qh; ++q) {
+        float2 X[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) X[e] = make_float2(0.f, 0.f);
+        const float2 *src = a.partial + ((int64_t)d * a.s.Qh + q) * a.nchunks * P + tid_opaque();
+        for (int c = 0; c < a.nchunks; ++c) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) X[e] = cadd(X[e], src[(int64_t)c * P + e * T]);
+        }
+        if (a.spec) {
+            float2 *sp = a.spec + ((int64_t)d * a.s.Qh + q) * P;
+#pragma unroll
+            for (int e = 0; e < E; ++e) sp[threadIdx.x + e * T] = X[e];
+        }
+        if (!a.out) continue;
+        store<P>(lds, X);
+        __syncthreads();
+        float2 Z[E];
+        inverse<P>(lds, a.s.twP, Z);
+        const int tt = tid_opaque();
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int k = tt + e * T;
+            for (int64_t m = k; m < a.Jt; m += P) {
+                const float t = inv_term(a.s, q, m, Z[e]);
+                float *dst = a.out + (int64_t)d * a.Jt + m;
+                *dst = (q == 0) ? t : *dst + t;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Spectrum of given sketches: one workgroup per (sketch, slice).
+// ---------------------------------------------------------------------------
+struct SpecArgs {
+    const float *y;
+    float2 *spec;
+    int64_t Jt;
+    SliceArgs s;
+};
+
+template <int P>
+__global__ __launch_bounds__(Shape<P>::T) void spectrum_kernel(SpecArgs a) {
+    extern __shared__ float2 lds[];
+    constexpr int E = Shape<P>::E;
+    constexpr int T = Shape<P>::T;
+    const int q = blockIdx.x % a.s.Qh;
+    const int d = blockIdx.x / a.s.Qh;
+    build_seq_slice<P>(lds, a.y + (int64_t)d * a.Jt, (int)a.Jt, q, a.s);
+    __syncthreads();
+    float2 v[E];
+    forward<P>(lds, a.s.twP, v);
+    float2 *sp = a.spec + ((int64_t)d * a.s.Qh + q) * P;
+#pragma unroll
+    for (int e = 0; e < E; ++e) sp[threadIdx.x + e * T] = v[e];
+}
+
+// ---------------------------------------------------------------------------
+// T(I, u, v)-type contraction (Section 4.1): one workgroup per (sketch d,
+// vector tuple p).  z = F^-1(X_d prod_{n != f} conj(F(CS_n(v_n)))) over all
+// slices, accumulated into zbuf[d][p][0..J_f); then
+// est[p][i][d] = s_f(i) z[h_f(i)].
+// ---------------------------------------------------------------------------
+struct FreeArgs {
+    const float2 *spec;
+    const float *vecs[FCS_MAX_ORDER];
+    const uint32_t *tab;
+    int64_t off[FCS_MAX_ORDER];
+    int64_t sumI;
+    const int32_t *inv;
+    int64_t ioff[FCS_MAX_ORDER];
+    int64_t iblock;
+    int I[FCS_MAX_ORDER];
+    int J[FCS_MAX_ORDER];
+    int N, D, Pn, free_mode;
+    SliceArgs s;
+    float *zbuf;            // [D][Pn][J_f]
+    float *est;             // [Pn][I_f][D]
+};
+
+template <int P>
+__global__ __launch_bounds__(Shape<P>::T) void free_mode_kernel(FreeArgs a) {
+    extern __shared__ float2 lds[];
+    constexpr int E = Shape<P>::E;
+    constexpr int T = Shape<P>::T;
+    const int p = blockIdx.x % a.Pn;
+    const int d = blockIdx.x / a.Pn;
+    const int f = a.free_mode;
+    const int Jf = a.J[f];
+    float *z = a.zbuf + ((int64_t)d * a.Pn + p) * Jf;
+    const int32_t *invd = a.inv + (int64_t)d * a.iblock;
+    for (int q = 0; q < a.s.Qh; ++q) {
+        float2 X[E];
+        const float2 *sp = a.spec + ((int64_t)d * a.s.Qh + q) * P;
+#pragma unroll
+        for (int e = 0; e < E; ++e) X[e] = sp[threadIdx.x + e * T];
+        for (int n = 0; n < a.N; ++n) {
+            if (n == f) continue;
+            const int32_t *off = invd + a.ioff[n];
+            build_cs_slice<P>(lds, a.vecs[n] + (int64_t)p * a.I[n], off, off + a.J[n] + 1, a.J[n], q, a.s, 1.0f);
+            __syncthreads();
+            float2 F[E];
+            forward<P>(lds, a.s.twP, F);
+#pragma unroll
+            for (int e = 0; e < E; ++e) X[e] = cmulc(X[e], F[e]);
+        }
+        store<P>(lds, X);
+        __syncthreads();
+        float2 Z[E];
+        inverse<P>(lds, a.s.twP, Z);
+        const int tt = tid_opaque();
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int k = tt + e * T;
+            for (int m = k; m < Jf; m += P) {
+                const float t = inv_term(a.s, q, m, Z[e]);
+                z[m] = (q == 0) ? t : z[m] + t;
+            }
+        }
+        __syncthreads();
+    }
+    __threadfence_block();
+    __syncthreads();
+    const uint32_t *tf = a.tab + (int64_t)d * a.sumI + a.off[f];
+    const int If = a.I[f];
+    for (int i = threadIdx.x; i < If; i += T) {
+        const uint32_t w = tf[i];
+        const float v = z[w & FCS_H_MASK];
+        a.est[((int64_t)p * If + i) * a.D + d] = __uint_as_float(__float_as_uint(v) ^ (w & FCS_S_BIT));
+    }
+}
+
+template <int MAXD>
+__global__ __launch_bounds__(256) void median_rows_kernel(const float *est, int64_t rows, int D, double *out) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= rows) return;
+    float v[MAXD];
+#pragma unroll
+    for (int d = 0; d < MAXD; ++d) v[d] = d < D ? est[k * D + d] : 0.f;
+    out[k] = fcs_median_reg<MAXD>(v, D);
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+SliceArgs slice_args(const fcs_plan *p) {
+    SliceArgs s;
+    s.twP = p->twP;
+    s.twL = p->twL;
+    s.L = (int)p->L;
+    s.P = (int)p->P;
+    s.Q = p->Q;
+    s.Qh = p->Qh;
+    return s;
+}
+
+int cp_chunks(const fcs_plan *p, int64_t R) {
+    if (R <= 0) return 1;
+    const int64_t tiles = (int64_t)p->D * p->Qh;
+    const int64_t waves = p->P >= 8192 ? 2 : 8;      // workgroups per CU that fit
+    const int64_t want = std::max<int64_t>(1, fcs_ceil_div(waves * fcs_device_cu_count(), tiles));
+    return (int)std::min<int64_t>(R, want);
+}
+
+template <typename K>
+void allow_lds_cp(K kernel, size_t bytes) {
+    if (bytes > 65536)
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+template <int P>
+void launch_cp(const CpArgs &ca, const FinArgs &fa, int D, int Qh, hipStream_t s) {
+    constexpr size_t lds = Lds<P>::bytes;
+    allow_lds_cp(cp_forward_kernel<P>, lds);
+    allow_lds_cp(cp_finalize_kernel<P>, lds);
+    hipLaunchKernelGGL(cp_forward_kernel<P>, dim3(D * Qh * ca.nchunks), dim3(Shape<P>::T), lds, s, ca);
+    hipLaunchKernelGGL(cp_finalize_kernel<P>, dim3(D), dim3(Shape<P>::T), lds, s, fa);
+}
+
+template <int P>
+void launch_spectrum(const SpecArgs &sa, int D, int Qh, hipStream_t s) {
+    constexpr size_t lds = Lds<P>::bytes;
+    allow_lds_cp(spectrum_kernel<P>, lds);
+    hipLaunchKernelGGL(spectrum_kernel<P>, dim3(D * Qh), dim3(Shape<P>::T), lds, s, sa);
+}
+
+template <int P>
+void launch_free(const FreeArgs &fa, hipStream_t s) {
+    constexpr size_t lds = Lds<P>::bytes;
+    allow_lds_cp(free_mode_kernel<P>, lds);
+    hipLaunchKernelGGL(free_mode_kernel<P>, dim3(fa.D * fa.Pn), dim3(Shape<P>::T), lds, s, fa);
+}
+
+#define FCS_DISPATCH_P(P_, CALL)                 \
+    switch (P_) {                                \
+    case 256: { constexpr int PP = 256; CALL; } break;     \
+    case 512: { constexpr int PP = 512; CALL; } break;     \
+    case 1024: { constexpr int PP = 1024; CALL; } break;   \
+    case 2048: { constexpr int PP = 2048; CALL; } break;   \
+    case 4096: { constexpr int PP = 4096; CALL; } break;   \
+    case 8192: { constexpr int PP = 8192; CALL; } break;   \
+    case 16384: { constexpr int PP = 16384; CALL; } break; \
+    default: FCS_FAIL(FCS_EUNSUPPORTED, "FFT size %lld not built", (long long)(P_)); \
+    }
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+size_t fcs_ws_cp(const fcs_plan *p, int64_t R) {
+    if (p->P == 0) return 256;
+    const int nch = cp_chunks(p, R);
+    return align256((size_t)p->D * p->Qh * nch * p->P * sizeof(float2));
+}
+
 size_t fcs_ws_spectrum(const fcs_plan *) { return 256; }
 
-extern "C" fcs_status fcs_sketch_cp(fcs_plan_t, int64_t, const float *const *, const float *, float *,
-                                    float *, void *, size_t, void *) {
-    FCS_FAIL(FCS_EUNSUPPORTED, "CP sketch not built yet");
+size_t fcs_ws_free_mode(const fcs_plan *p, int64_t Pn) {
+    if (Pn <= 0) return 256;
+    int64_t Jmax = 0, Imax = 0;
+    for (int n = 0; n < p->N; ++n) {
+        Jmax = std::max<int64_t>(Jmax, p->J[n]);
+        Imax = std::max<int64_t>(Imax, p->I[n]);
+    }
+    return align256((size_t)p->D * Pn * Jmax * 4) + align256((size_t)Pn * Imax * p->D * 4);
 }
 
-extern "C" fcs_status fcs_sketch_spectrum(fcs_plan_t, const float *, float *, void *, size_t, void *) {
-    FCS_FAIL(FCS_EUNSUPPORTED, "spectrum not built yet");
+extern "C" fcs_status fcs_sketch_cp(fcs_plan_t p, int64_t R, const float *const *U, const float *lambda,
+                                    float *out, float *spec, void *ws, size_t ws_bytes, void *stream) {
+    fcs_clear_error();
+    if (!p || !p->bound) FCS_FAIL(FCS_EINVAL, "plan is null or not bound");
+    if (p->P == 0) FCS_FAIL(FCS_EUNSUPPORTED, "no transform length fits this plan");
+    if (R < 0) FCS_FAIL(FCS_EINVAL, "R < 0");
+    if (R > INT32_MAX) FCS_FAIL(FCS_EUNSUPPORTED, "R too large");
+    if (!out && !spec) FCS_FAIL(FCS_EINVAL, "neither out nor spec given");
+    if (R > 0 && !U) FCS_FAIL(FCS_EINVAL, "null factor array");
+    for (int n = 0; R > 0 && n < p->N; ++n)
+        if (!U[n]) FCS_FAIL(FCS_EINVAL, "null factor %d", n);
+    hipStream_t s = (hipStream_t)stream;
+    if (R == 0) {
+        if (out) {
+            fcs_status st = fcs_zero_fill(out, (int64_t)p->D * p->Jt, s);
+            if (st != FCS_OK) return st;
+        }
+        if (spec) return fcs_zero_fill(spec, (int64_t)p->D * p->Qh * p->P * 2, s);
+        return FCS_OK;
+    }
+    const size_t need = fcs_ws_cp(p, R);
+    if (!ws || ws_bytes < need) FCS_FAIL(FCS_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, need);
+    if (!fcs_aligned(ws, 16)) FCS_FAIL(FCS_EINVAL, "workspace not 16-byte aligned");
+    CpArgs ca{};
+    for (int n = 0; n < p->N; ++n) {
+        ca.U[n] = U[n];
+        ca.I[n] = (int)p->I[n];
+        ca.J[n] = (int)p->J[n];
+        ca.ioff[n] = p->ioff[n];
+    }
+    ca.lambda = lambda;
+    ca.inv = p->inv;
+    ca.iblock = p->iblock;
+    ca.N = p->N;
+    ca.D = p->D;
+    ca.R = (int)R;
+    ca.nchunks = cp_chunks(p, R);
+    ca.rchunk = (int)fcs_ceil_div(R, ca.nchunks);
+    ca.s = slice_args(p);
+    ca.partial = (float2 *)ws;
+    FinArgs fa{};
+    fa.partial = ca.partial;
+    fa.nchunks = ca.nchunks;
+    fa.s = ca.s;
+    fa.out = out;
+    fa.spec = (float2 *)spec;
+    fa.Jt = p->Jt;
+    FCS_DISPATCH_P(p->P, (launch_cp<PP>(ca, fa, p->D, p->Qh, s)));
+    FCS_LAUNCH_CHECK();
+    return FCS_OK;
 }
 
-extern "C" fcs_status fcs_contract_free_mode(fcs_plan_t, const float *, int32_t, int64_t,
-                                             const float *const *, double *, void *, size_t, void *) {
-    FCS_FAIL(FCS_EUNSUPPORTED, "free-mode contraction not built yet");
+extern "C" fcs_status fcs_sketch_spectrum(fcs_plan_t p, const float *y, float *spec, void *ws, size_t ws_bytes,
+                                          void *stream) {
+    fcs_clear_error();
+    (void)ws;
+    (void)ws_bytes;
+    if (!p || !p->bound) FCS_FAIL(FCS_EINVAL, "plan is null or not bound");
+    if (p->P == 0) FCS_FAIL(FCS_EUNSUPPORTED, "no transform length fits this plan");
+    if (!y || !spec) FCS_FAIL(FCS_EINVAL, "null sketch or spectrum");
+    SpecArgs sa{};
+    sa.y = y;
+    sa.spec = (float2 *)spec;
+    sa.Jt = p->Jt;
+    sa.s = slice_args(p);
+    hipStream_t s = (hipStream_t)stream;
+    FCS_DISPATCH_P(p->P, (launch_spectrum<PP>(sa, p->D, p->Qh, s)));
+    FCS_LAUNCH_CHECK();
+    return FCS_OK;
+}
+
+extern "C" fcs_status fcs_contract_free_mode(fcs_plan_t p, const float *spec, int32_t free_mode, int64_t Pn,
+                                             const float *const *vecs, double *out, void *ws, size_t ws_bytes,
+                                             void *stream) {
+    fcs_clear_error();
+    if (!p || !p->bound) FCS_FAIL(FCS_EINVAL, "plan is null or not bound");
+    if (p->P == 0) FCS_FAIL(FCS_EUNSUPPORTED, "no transform length fits this plan");
+    if (free_mode < 0 || free_mode >= p->N) FCS_FAIL(FCS_EINVAL, "free_mode %d out of range", free_mode);
+    if (Pn < 0) FCS_FAIL(FCS_EINVAL, "P < 0");
+    if (Pn == 0) return FCS_OK;
+    if (Pn > INT32_MAX / std::max<int>(1, p->D)) FCS_FAIL(FCS_EUNSUPPORTED, "too many vector tuples");
+    if (!spec || !out || !vecs) FCS_FAIL(FCS_EINVAL, "null spectrum, output or vector array");
+    for (int n = 0; n < p->N; ++n)
+        if (n != free_mode && !vecs[n]) FCS_FAIL(FCS_EINVAL, "null vector block %d", n);
+    const size_t need = fcs_ws_free_mode(p, Pn);
+    if (!ws || ws_bytes < need) FCS_FAIL(FCS_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, need);
+    if (!fcs_aligned(ws, 16)) FCS_FAIL(FCS_EINVAL, "workspace not 16-byte aligned");
+    int64_t Jmax = 0;
+    for (int n = 0; n < p->N; ++n) Jmax = std::max<int64_t>(Jmax, p->J[n]);
+    FreeArgs fa{};
+    fa.spec = (const float2 *)spec;
+    for (int n = 0; n < p->N; ++n) {
+        fa.vecs[n] = n == free_mode ? nullptr : vecs[n];
+        fa.off[n] = p->off[n];
+        fa.ioff[n] = p->ioff[n];
+        fa.I[n] = (int)p->I[n];
+        fa.J[n] = (int)p->J[n];
+    }
+    fa.tab = p->tab;
+    fa.sumI = p->sumI;
+    fa.inv = p->inv;
+    fa.iblock = p->iblock;
+    fa.N = p->N;
+    fa.D = p->D;
+    fa.Pn = (int)Pn;
+    fa.free_mode = free_mode;
+    fa.s = slice_args(p);
+    fa.zbuf = (float *)ws;
+    fa.est = (float *)((char *)ws + align256((size_t)p->D * Pn * Jmax * 4));
+    hipStream_t s = (hipStream_t)stream;
+    FCS_DISPATCH_P(p->P, (launch_free<PP>(fa, s)));
+    FCS_LAUNCH_CHECK();
+    const int64_t rows = Pn * p->I[free_mode];
+    const unsigned grid = (unsigned)fcs_ceil_div(rows, 256);
+    if (p->D <= 8)
+        median_rows_kernel<8><<<grid, 256, 0, s>>>(fa.est, rows, p->D, out);
+    else if (p->D <= 16)
+        median_rows_kernel<16><<<grid, 256, 0, s>>>(fa.est, rows, p->D, out);
+    else if (p->D <= 32)
+        median_rows_kernel<32><<<grid, 256, 0, s>>>(fa.est, rows, p->D, out);
+    else
+        median_rows_kernel<64><<<grid, 256, 0, s>>>(fa.est, rows, p->D, out);
+    FCS_LAUNCH_CHECK();
+    return FCS_OK;
 }

@@ -29,10 +29,16 @@ struct fcs_plan {
     int64_t L = 0, P = 0;              // transform length L = Q * P, FFT size P
     int Q = 0, Qh = 0;                 // slices, stored slices floor(Q/2)+1
     // device layout inside the caller's table buffer
-    size_t tab_off = 0, twP_off = 0, twL_off = 0, total = 0;
+    size_t tab_off = 0, twP_off = 0, twL_off = 0, inv_off = 0, total = 0;
     const uint32_t *tab = nullptr;     // D x sumI packed hash words
     const float2 *twP = nullptr;       // exp(-2 pi i k / P), k < P
     const float2 *twL = nullptr;       // exp(-2 pi i k / L), k < L
+    // inverse hash lists (buckets of h_n), per sketch a block of iblock words:
+    // for mode n at ioff[n]: J_n + 1 bucket offsets, then I_n entries
+    // (index i | sign bit), entries of bucket j at [off[j], off[j+1])
+    const int32_t *inv = nullptr;
+    int64_t ioff[FCS_MAX_ORDER] = {0};
+    int64_t iblock = 0;
     // largest number of mode-0 indices that share one h_0 value, over all
     // sketches (bounds the additions one row makes to one bin); INT32_MAX
     // when too large to evaluate on the host

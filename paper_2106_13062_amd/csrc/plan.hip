@@ -210,6 +210,13 @@ extern "C" fcs_status fcs_plan_create(const fcs_plan_desc *desc, fcs_plan_t *out
     cur = align256(cur + (size_t)tmp.P * sizeof(float2));
     tmp.twL_off = cur;
     cur = align256(cur + (size_t)tmp.L * sizeof(float2));
+    tmp.iblock = 0;
+    for (int n = 0; n < tmp.N; ++n) {
+        tmp.ioff[n] = tmp.iblock;
+        tmp.iblock += tmp.J[n] + 1 + tmp.I[n];
+    }
+    tmp.inv_off = cur;
+    cur = align256(cur + (size_t)tmp.D * (size_t)tmp.iblock * sizeof(int32_t));
     tmp.total = cur;
     fcs_plan *p = new (std::nothrow) fcs_plan(tmp);
     if (!p) FCS_FAIL(FCS_ENOMEM, "host allocation of the plan failed");
@@ -218,6 +225,41 @@ extern "C" fcs_status fcs_plan_create(const fcs_plan_desc *desc, fcs_plan_t *out
 }
 
 extern "C" size_t fcs_plan_table_bytes(fcs_plan_t p) { return p ? p->total : 0; }
+
+// Inverse hash lists (bucket offsets and entries per sketch and mode),
+// computed with the same hash function on the host and copied to the
+// plan's table memory.  Synchronises the stream.
+static fcs_status build_inverse(const fcs_plan *p, int32_t *dev_inv, hipStream_t s) {
+    std::vector<int32_t> host((size_t)p->D * (size_t)p->iblock);
+    const uint64_t sm = sm64_mix(p->seed);
+    for (int d = 0; d < p->D; ++d) {
+        for (int n = 0; n < p->N; ++n) {
+            int32_t *blk = host.data() + (size_t)d * p->iblock + p->ioff[n];
+            const int64_t In = p->I[n], Jn = p->J[n];
+            int32_t *off = blk;
+            int32_t *ent = blk + Jn + 1;
+            std::vector<uint32_t> word((size_t)In);
+            const uint64_t key = sm64_mix(sm + ((uint64_t)d << 16) + (uint64_t)n);
+            for (int64_t j = 0; j <= Jn; ++j) off[j] = 0;
+            for (int64_t i = 0; i < In; ++i) {
+                const uint64_t y = sm64_mix(key + (uint64_t)i);
+                const uint32_t h = (uint32_t)(((y >> 32) * (uint64_t)Jn) >> 32);
+                word[(size_t)i] = h | ((y & 1ull) ? FCS_S_BIT : 0u);
+                off[h + 1] += 1;
+            }
+            for (int64_t j = 0; j < Jn; ++j) off[j + 1] += off[j];
+            std::vector<int32_t> fill(off, off + Jn);
+            for (int64_t i = 0; i < In; ++i) {
+                const uint32_t w = word[(size_t)i];
+                const uint32_t h = w & FCS_H_MASK;
+                ent[fill[h]++] = (int32_t)((uint32_t)i | (w & FCS_S_BIT));
+            }
+        }
+    }
+    FCS_HIP_CHECK(hipMemcpyAsync(dev_inv, host.data(), host.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    FCS_HIP_CHECK(hipStreamSynchronize(s));
+    return FCS_OK;
+}
 
 // Largest multiplicity of h_0 values over all sketches, evaluated with the
 // same hash function on the host (small plans only).
@@ -271,6 +313,11 @@ extern "C" fcs_status fcs_plan_bind(fcs_plan_t p, void *dev_tables, void *stream
         FCS_LAUNCH_CHECK();
     }
     p->m0 = mode0_multiplicity(p);
+    {
+        fcs_status st = build_inverse(p, (int32_t *)(base + p->inv_off), s);
+        if (st != FCS_OK) return st;
+    }
+    p->inv = (const int32_t *)(base + p->inv_off);
     p->tab = (const uint32_t *)(base + p->tab_off);
     p->twP = (const float2 *)(base + p->twP_off);
     p->twL = (const float2 *)(base + p->twL_off);

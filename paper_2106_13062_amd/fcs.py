@@ -169,6 +169,8 @@ class Plan:
         """vecs: list of N entries; vecs[free_mode] is ignored (may be None);
         the others are float32 P x I_n."""
         _need(spec, torch.float32, "spec")
+        if not 0 <= int(free_mode) < self.N:
+            raise ValueError(f"free_mode must be in [0, {self.N})")
         Pn = None
         ptrs = (ctypes.c_void_p * self.N)()
         for n in range(self.N):
