@@ -89,7 +89,7 @@ def dense_workload(args, torch, dev):
         cpu = dense_cpu_baseline(cfg, T, plan.Jt, args.cpu_rows)
     del Td
     torch.cuda.empty_cache()
-    return cfg, res, cpu
+    return cfg, res, cpu, T
 
 
 def dense_cpu_baseline(cfg, T, Jt, sample_rows):
@@ -109,6 +109,86 @@ def dense_cpu_baseline(cfg, T, Jt, sample_rows):
                       f"all {cfg.D} sketches, {dt:.2f} s, scaled to the full tensor"}
 
 
+def cp_workload(args, torch, dev, cfg, pairs=0):
+    """CP sketch (and optionally T(I, u, v) for `pairs` vector pairs)."""
+    import synth
+    from paper_2106_13062_amd import Plan
+    U = cfg.factors()
+    plan = Plan(cfg.I, cfg.J, cfg.D, cfg.hash_seed, device=dev)
+    Ud = [torch.from_numpy(np.ascontiguousarray(u.T)).to(dev) for u in U]
+    R = cfg.R
+    out = torch.empty((cfg.D, plan.Jt), dtype=torch.float32, device=dev)
+    spec = torch.empty((cfg.D, plan.spec_len, 2), dtype=torch.float32, device=dev)
+    ws = plan.workspace(2, R=R)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        plan.sketch_cp(Ud, out=out, spec=spec, want_spec=True, ws=ws, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    ms, _ = event_timer(torch, stream, step, max(3, args.steps // 2))
+    lg = np.log2(plan.P)
+    # forward transforms: D sketches x stored slices x R ranks x N modes,
+    # 5 P log2 P flops each (the usual complex radix-2 count)
+    fft_flop = cfg.D * (plan.Q // 2 + 1) * R * len(cfg.I) * 5.0 * plan.P * lg
+    res = {"workload": cfg.name, "I": list(cfg.I), "J": list(cfg.J), "R": R, "D": cfg.D, "L": plan.L,
+           "P": plan.P, "Q": plan.Q, "ms": ms, "sketches_per_s": cfg.D / (ms * 1e-3),
+           "fft_gflop": fft_flop / 1e9, "fft_tflops": fft_flop / (ms * 1e-3) / 1e12,
+           "frac_fp32_peak": fft_flop / (ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS}
+    if pairs:
+        uv = synth.unit_vectors(cfg.data_seed, 2 * pairs, cfg.I[1], stream=5)
+        u = torch.from_numpy(uv[:pairs]).to(dev)
+        v = torch.from_numpy(uv[pairs:]).to(dev)
+        outv = torch.empty((pairs, cfg.I[0]), dtype=torch.float64, device=dev)
+        wsf = plan.workspace(4, P=pairs)
+
+        def contract():
+            plan.contract_free_mode(spec, 0, [None, u, v], out=outv, ws=wsf, stream=stream)
+
+        contract()
+        cms, _ = event_timer(torch, stream, contract, max(3, args.steps // 2))
+        res.update({"pairs": pairs, "contract_ms": cms, "contractions_per_s": pairs / (cms * 1e-3)})
+    return res
+
+
+def coo_workload(args, torch, dev, T):
+    """10 % Bernoulli COO copy of the dense tensor, int32 coordinates."""
+    import synth
+    from paper_2106_13062_amd import Plan
+    cfg = synth.DENSE1024
+    idx, val = synth.bernoulli_coo(cfg.data_seed, T, cfg.I, cfg.density)
+    nnz = val.size
+    idx_d = torch.from_numpy(idx).to(dev)
+    val_d = torch.from_numpy(val).to(dev)
+    del idx, val
+    plan = Plan(cfg.I, cfg.J, cfg.D, cfg.hash_seed, device=dev)
+    out = torch.empty((cfg.D, plan.Jt), dtype=torch.float32, device=dev)
+    ws = plan.workspace(1)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        plan.sketch_coo(idx_d, val_d, out=out, ws=ws, stream=stream)
+
+    for _ in range(args.warmup):
+        step()
+    ms, _ = event_timer(torch, stream, step, max(3, args.steps // 2))
+    alg = 16 * nnz
+    return {"workload": "dense1024 10% COO", "nnz": nnz, "ms": ms, "sketches_per_s": cfg.D / (ms * 1e-3),
+            "alg_bytes": alg, "achieved_gbs": alg / (ms * 1e-3) / 1e9}
+
+
+def copy_calibration(torch, dev, nbytes=1 << 30, reps=5):
+    """A plain device-to-device copy of known size, for scaling the
+    FETCH_SIZE / WRITE_SIZE counters of the profiled kernels."""
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).uniform_()
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes, "reps": reps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -118,6 +198,9 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=1 << 19,
                     help="rows of the tensor the CPU oracle sketches")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "dense1024_traffic.json"))
+    ap.add_argument("--mode", default="full", choices=["full", "dense", "copy"],
+                    help="full: headline + secondary workloads; dense: headline only; "
+                         "copy: plain copy kernel for counter calibration")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -130,7 +213,20 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
 
-    cfg, res, cpu = dense_workload(args, torch, dev)
+    if args.mode == "copy":
+        copy_calibration(torch, dev)
+        return
+    cfg, res, cpu, T = dense_workload(args, torch, dev)
+    secondary = {}
+    if args.mode == "full":
+        import synth
+        log("secondary: cp100")
+        secondary["cp100"] = cp_workload(args, torch, dev, synth.CP100)
+        log("secondary: cp10k + T(I,u,v)")
+        secondary["cp10k"] = cp_workload(args, torch, dev, synth.CP10K, pairs=synth.CP10K.pairs)
+        log("secondary: coo")
+        secondary["coo"] = coo_workload(args, torch, dev, T)
+    del T
     traffic = None
     if os.path.exists(args.traffic_json):
         with open(args.traffic_json) as f:
@@ -156,6 +252,7 @@ def main():
                      "kernel": "dense_scatter_kernel", "launch_ms": res["event_ms"],
                      "alg_bytes_per_launch": res["alg_bytes"]},
         "cpu_baseline": cpu,
+        "secondary": secondary,
     }
     print(json.dumps(line), flush=True)
 

@@ -36,22 +36,71 @@ struct SliceArgs {
 
 // Slice q of the DFT of one mode's count sketch CS_n(u): builds w_q in LDS
 // (natural order, padded).  u is the factor column (I_n floats), the inverse
-// lists give the buckets of h_n.  Each thread writes its own positions.
+// lists give the buckets of h_n.  Each thread writes its own positions.  The
+// loads are issued in batches over the thread's E positions (bucket bounds,
+// then first entries, then factor values) so that their latencies overlap;
+// buckets with more than one entry (rare when J_n >= I_n) finish in a loop.
 template <int P>
 __device__ __forceinline__ void build_cs_slice(float2 *lds, const float *__restrict__ u,
                                                const int32_t *__restrict__ off,
                                                const int32_t *__restrict__ ent, int Jn, int q,
                                                const SliceArgs &s, float scale) {
     constexpr int T = Shape<P>::T;
-    for (int m = tid_opaque(); m < P; m += T) {
+    constexpr int E = Shape<P>::E;
+    const int t = tid_opaque();
+    if (Jn <= P) {
+        // positions t + e*T in groups of G (smaller groups for 1024-thread
+        // workgroups, whose register budget is half)
+        constexpr int G = (T >= 1024) ? E / 4 : E;
+#pragma unroll
+        for (int g0 = 0; g0 < E; g0 += G) {
+            int b0[G], b1[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const int j = t + (g0 + g) * T;
+                const bool in = j < Jn;
+                b0[g] = in ? off[j] : 0;
+                b1[g] = in ? off[j + 1] : 0;
+            }
+            uint32_t e0[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) e0[g] = (b1[g] > b0[g]) ? (uint32_t)ent[b0[g]] : 0u;
+            float y[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const float v = (b1[g] > b0[g]) ? u[e0[g] & FCS_H_MASK] : 0.f;
+                y[g] = __uint_as_float(__float_as_uint(v) ^ (e0[g] & FCS_S_BIT));
+            }
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                for (int k = b0[g] + 1; k < b1[g]; ++k) {
+                    const uint32_t w = (uint32_t)ent[k];
+                    y[g] += __uint_as_float(__float_as_uint(u[w & FCS_H_MASK]) ^ (w & FCS_S_BIT));
+                }
+            }
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const int m = t + (g0 + g) * T;
+                const float ys = y[g] * scale;
+                if (q == 0) {
+                    lds[pad(m)] = make_float2(ys, 0.f);
+                } else {
+                    const float2 w = s.twL[(int)(((int64_t)q * m) % s.L)];
+                    lds[pad(m)] = make_float2(ys * w.x, ys * w.y);
+                }
+            }
+        }
+        return;
+    }
+    // J_n > P: fold the buckets of m, m + P, m + 2P, ... onto position m
+    for (int m = t; m < P; m += T) {
         float2 acc = make_float2(0.f, 0.f);
         for (int j = m; j < Jn; j += P) {
             float y = 0.f;
-            const int b0 = off[j], b1 = off[j + 1];
-            for (int k = b0; k < b1; ++k) {
-                const uint32_t e = (uint32_t)ent[k];
-                const float v = u[e & FCS_H_MASK];
-                y += __uint_as_float(__float_as_uint(v) ^ (e & FCS_S_BIT));
+            const int c0 = off[j], c1 = off[j + 1];
+            for (int k = c0; k < c1; ++k) {
+                const uint32_t w = (uint32_t)ent[k];
+                y += __uint_as_float(__float_as_uint(u[w & FCS_H_MASK]) ^ (w & FCS_S_BIT));
             }
             if (q == 0) {
                 acc.x += y;
