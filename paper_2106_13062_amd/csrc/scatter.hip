@@ -30,8 +30,9 @@
 //    visits.  A wave owns a 256-column segment (one 16-byte load per lane) of
 //    the rows it visits; its lanes keep the LDS byte address of bin h_0(i_0)
 //    and the sign of s_0(i_0) of every sketch of the group in registers.  Per
-//    element and sketch: one v_bitop3 (sign), one v_cvt_rpi (round), one
-//    v_add (address) and one ds_add_u32.
+//    element: one scale, one range test, one v_cvt_rpi (round); per element
+//    and sketch: one v_mul_i32_i24 (column sign), one v_add (address) and
+//    one ds_add_u32 or ds_sub_u32 (the row sign, uniform per wave).
 //  * When N >= 2 a workgroup's rows share the last-mode index, so its bins lie
 //    in h_{N-1}(i_{N-1}) + [0, J~ - J_{N-1} + 1) and only that window is held
 //    (the last mode's sign is applied at the flush).  Sketches are split into
@@ -80,12 +81,6 @@ struct DenseArgs {
     int nrow_modes;          // modes 1..nrow_modes vary along a block's rows
 };
 
-__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
-    uint32_t r;
-    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "v"(c));
-    return r;
-}
-
 // round to nearest (ties up) and convert: one VALU op
 __device__ __forceinline__ int cvt_rpi(float x) {
     int r;
@@ -94,6 +89,18 @@ __device__ __forceinline__ int cvt_rpi(float x) {
 }
 
 __device__ __forceinline__ int64_t fcs_ceil_div_dev(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// LDS atomics on 32-bit LDS byte addresses: the base of the dynamic LDS
+// array is folded into the per-lane addresses once, so each atomic needs a
+// single v_add (lane address + uniform row offset)
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+__device__ __forceinline__ uint32_t lds_addr(uint32_t *p) { return (uint32_t)(uintptr_t)(lds_u32 *)p; }
+__device__ __forceinline__ void lds_add(uint32_t addr, uint32_t v) {
+    __hip_atomic_fetch_add((lds_u32 *)(uintptr_t)addr, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_sub(uint32_t addr, uint32_t v) {
+    __hip_atomic_fetch_sub((lds_u32 *)(uintptr_t)addr, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
 
 __device__ inline void dense_block_map(const DenseArgs &a, int64_t bid, int64_t &blk, int &grp) {
     const int64_t span = (int64_t)NXCD * a.ngroups;
@@ -117,8 +124,8 @@ __device__ __forceinline__ void load_seg(const float *row, int lane, const bool 
 // Out-of-range or non-finite entries of one row segment: float atomics into
 // the HBM sketch, with every sign including the slab's last-mode sign.
 template <int DG, bool CHECK>
-__device__ __forceinline__ void scatter_slow(const DenseArgs &a, const float (&x)[4], float scale, int d0,
-                                             const uint32_t (&A)[DG][4], const uint32_t (&M)[DG][4],
+__device__ __forceinline__ void scatter_slow(const DenseArgs &a, uint32_t qaddr, const float (&x)[4], float scale,
+                                             int d0, const uint32_t (&A)[DG][4], const int (&S)[DG][4],
                                              const bool (&valid)[4], const uint32_t (&C)[DG],
                                              const uint32_t (&R)[DG], const int (&base)[DG],
                                              const uint32_t (&wsign)[DG]) {
@@ -128,8 +135,8 @@ __device__ __forceinline__ void scatter_slow(const DenseArgs &a, const float (&x
         if ((!CHECK || valid[e]) && !(fabsf(xe * scale) < QLIM)) {
 #pragma unroll
             for (int d = 0; d < DG; ++d) {
-                const int bin = (int)((A[d][e] + C[d]) / 4u) - d * a.W;
-                const uint32_t sg = M[d][e] ^ R[d] ^ wsign[d];
+                const int bin = (int)((A[d][e] + C[d] - qaddr) / 4u) - d * a.W;
+                const uint32_t sg = (S[d][e] < 0 ? FCS_S_BIT : 0u) ^ R[d] ^ wsign[d];
                 unsafeAtomicAdd(a.out + (int64_t)(d0 + d) * a.Jt + base[d] + bin,
                                 __uint_as_float(__float_as_uint(xe) ^ sg));
             }
@@ -138,36 +145,37 @@ __device__ __forceinline__ void scatter_slow(const DenseArgs &a, const float (&x
 }
 
 // Add one row segment (4 values per lane) to the DG fixed-point windows.
-// The in-range test is per element; a wave with any out-of-range element
-// in the row takes the slow path for those elements (uniform branch).
+// Each value is scaled and rounded once (v_cvt_rpi); the column sign of
+// every sketch is a 24-bit integer multiply by +-1 and the row sign, uniform
+// across the wave, selects ds_sub_u32 instead of ds_add_u32.  A wave with an
+// out-of-range element in the row takes the float path for those elements.
 template <int DG, bool CHECK>
-__device__ __forceinline__ void scatter_seg(const DenseArgs &a, uint32_t *qbins, const float (&x)[4], float scale,
-                                            int d0, const uint32_t (&A)[DG][4], const uint32_t (&M)[DG][4],
+__device__ __forceinline__ void scatter_seg(const DenseArgs &a, uint32_t qaddr, const float (&x)[4], float scale,
+                                            int d0, const uint32_t (&A)[DG][4], const int (&S)[DG][4],
                                             const bool (&valid)[4], const uint32_t (&C)[DG],
                                             const uint32_t (&R)[DG], const int (&base)[DG],
                                             const uint32_t (&wsign)[DG]) {
-    float xs[4];
+    int q[4];
     bool slow = false;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-        xs[e] = x[e] * scale;
-        const bool ok = fabsf(xs[e]) < QLIM;     // false for NaN / Inf too
+        const float xs = x[e] * scale;
+        const bool ok = fabsf(xs) < QLIM;         // false for NaN / Inf too
         slow |= (!ok) && (!CHECK || valid[e]);
+        q[e] = cvt_rpi(ok ? xs : 0.f);
     }
-    if (__builtin_expect(__builtin_amdgcn_ballot_w64(slow) != 0, 0)) {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) xs[e] = fabsf(xs[e]) < QLIM ? xs[e] : 0.f;
-        scatter_slow<DG, CHECK>(a, x, scale, d0, A, M, valid, C, R, base, wsign);
-    }
+    if (__builtin_expect(__builtin_amdgcn_ballot_w64(slow) != 0, 0))
+        scatter_slow<DG, CHECK>(a, qaddr, x, scale, d0, A, S, valid, C, R, base, wsign);
 #pragma unroll
     for (int d = 0; d < DG; ++d) {
+        if (R[d]) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            if (!CHECK || valid[e]) {
-                const int q = cvt_rpi(__uint_as_float(xor3(__float_as_uint(xs[e]), M[d][e], R[d])));
-                uint32_t *dst = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(qbins) + (A[d][e] + C[d]));
-                __hip_atomic_fetch_add(dst, (uint32_t)q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            }
+            for (int e = 0; e < 4; ++e)
+                if (!CHECK || valid[e]) lds_sub(A[d][e] + C[d], (uint32_t)__mul24(q[e], S[d][e]));
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (!CHECK || valid[e]) lds_add(A[d][e] + C[d], (uint32_t)__mul24(q[e], S[d][e]));
         }
     }
 }
@@ -223,7 +231,9 @@ __device__ __forceinline__ void wave_rows(const DenseArgs &a, uint32_t *qbins, f
                                           int64_t nk, int wps, int64_t pk, int64_t nperiods, const int (&base)[DG],
                                           const uint32_t (&wsign)[DG]) {
     const int W = a.W;
-    uint32_t A[DG][4], M[DG][4];
+    const uint32_t qaddr = lds_addr(qbins);
+    uint32_t A[DG][4];
+    int S[DG][4];
     bool valid[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
@@ -232,12 +242,14 @@ __device__ __forceinline__ void wave_rows(const DenseArgs &a, uint32_t *qbins, f
 #pragma unroll
         for (int d = 0; d < DG; ++d) {
             const uint32_t p = valid[e] ? a.tab[(int64_t)(d0 + d) * a.sumI + col] : 0u;
-            A[d][e] = (uint32_t)((d * W + (int)(p & FCS_H_MASK)) * 4);
-            M[d][e] = p & FCS_S_BIT;
+            A[d][e] = qaddr + (uint32_t)((d * W + (int)(p & FCS_H_MASK)) * 4);
+            S[d][e] = (p & FCS_S_BIT) ? -1 : 1;
         }
     }
     const float *Tseg = a.T + (int64_t)seg * SEG;
     const int64_t rstride = (int64_t)wps * a.I0;
+    // b0 holds the even rows k, b1 the odd ones; row k + 2 is loaded into
+    // the buffer of row k as soon as row k is consumed
     float b0[4], b1[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
@@ -249,29 +261,30 @@ __device__ __forceinline__ void wave_rows(const DenseArgs &a, uint32_t *qbins, f
     uint32_t CR[DG];
     row_words<DG, NV>(a, d0, r_first, lane, wps, active && lane < nk, CR);
 
+    auto row = [&](int64_t k, float (&buf)[4]) {
+        uint32_t C[DG], R[DG];
+#pragma unroll
+        for (int d = 0; d < DG; ++d) {
+            const uint32_t w = __builtin_amdgcn_readlane(CR[d], (int)(k & 63));
+            C[d] = w & FCS_H_MASK;
+            R[d] = w & FCS_S_BIT;
+        }
+        float x[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) x[e] = buf[e];
+        if (k + 2 < nk) load_seg<VEC4, FULL>(Tseg + (r_first * a.I0 + (k + 2) * rstride), lane, valid, buf);
+        scatter_seg<DG, !FULL>(a, qaddr, x, scale, d0, A, S, valid, C, R, base, wsign);
+    };
+
     for (int64_t p = 0; p < nperiods; ++p) {
         const int64_t kb = p * pk;
         const int64_t ke = min(kb + pk, active ? nk : (int64_t)0);
-        for (int64_t k = kb; k < ke; ++k) {
+        int64_t k = kb;
+        if (k < ke && (k & 1)) row(k++, b1);     // odd k: never a 64-row boundary
+        for (; k < ke; k += 2) {
             if ((k & 63) == 0 && k > 0) row_words<DG, NV>(a, d0, r_first + k * wps, lane, wps, k + lane < nk, CR);
-            uint32_t C[DG], R[DG];
-#pragma unroll
-            for (int d = 0; d < DG; ++d) {
-                const uint32_t w = __builtin_amdgcn_readlane(CR[d], (int)(k & 63));
-                C[d] = w & FCS_H_MASK;
-                R[d] = w & FCS_S_BIT;
-            }
-            float x[4];
-            if (k & 1) {
-#pragma unroll
-                for (int e = 0; e < 4; ++e) x[e] = b1[e];
-                if (k + 2 < nk) load_seg<VEC4, FULL>(Tseg + (r_first * a.I0 + (k + 2) * rstride), lane, valid, b1);
-            } else {
-#pragma unroll
-                for (int e = 0; e < 4; ++e) x[e] = b0[e];
-                if (k + 2 < nk) load_seg<VEC4, FULL>(Tseg + (r_first * a.I0 + (k + 2) * rstride), lane, valid, b0);
-            }
-            scatter_seg<DG, !FULL>(a, qbins, x, scale, d0, A, M, valid, C, R, base, wsign);
+            row(k, b0);
+            if (k + 1 < ke) row(k + 1, b1);
         }
         __syncthreads();
         // period flush: integer bins -> float register accumulators (exact
@@ -289,7 +302,9 @@ __device__ __forceinline__ void wave_rows(const DenseArgs &a, uint32_t *qbins, f
 }
 
 template <int DG, int NV, bool VEC4, bool FULL>
-__global__ __launch_bounds__(DS_THREADS) void dense_scatter_kernel(DenseArgs a) {
+// one workgroup per CU when the window fills LDS: allow 2 waves per SIMD
+__global__ __launch_bounds__(DS_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2))) void dense_scatter_kernel(
+    DenseArgs a) {
     extern __shared__ uint32_t qbins[];     // DG x W fixed-point bins
     int64_t blk;
     int grp;
@@ -367,13 +382,14 @@ __global__ __launch_bounds__(DS_THREADS) void dense_scatter_kernel(DenseArgs a) 
     for (int m = 0; m < MAXACC; ++m) acc[m] = 0.f;
 
     // each wave owns at most one (segment, row lane) of the block
-    const int wps = max(1, DS_WAVES / nseg);             // waves per segment
+    // waves per segment; at most `period` so that pk * wps <= period
+    const int wps = max(1, min(DS_WAVES / nseg, a.period));
     const int64_t nrows = r1 - r0;
     const bool active = wave < nseg * wps;
     const int seg = s0 + (active ? wave % nseg : 0);
     const int rl = active ? wave / nseg : 0;
     const int64_t nk = (active && rl < nrows) ? (nrows - rl + wps - 1) / wps : 0;
-    const int64_t pk = max<int64_t>(1, a.period / wps);
+    const int64_t pk = a.period / wps;                   // >= 1
     const int64_t nperiods = (fcs_ceil_div_dev(nrows, wps) + pk - 1) / pk;
     // FULL kernels are launched only when every segment is complete
     wave_rows<DG, NV, VEC4, FULL>(a, qbins, acc, scale, inv, d0, seg, lane, active, r0 + rl, nk, wps, pk, nperiods,
