@@ -143,7 +143,8 @@ enum {
     FCS_OP_CP = 2,           /* fcs_sketch_cp with rank R                   */
     FCS_OP_INNER = 3,        /* fcs_contract_inner                          */
     FCS_OP_FREE_MODE = 4,    /* fcs_contract_free_mode with P pairs         */
-    FCS_OP_SPECTRUM = 5      /* fcs_sketch_spectrum                         */
+    FCS_OP_SPECTRUM = 5,     /* fcs_sketch_spectrum                         */
+    FCS_OP_KRON = 6          /* fcs_sketch_kron                             */
 };
 
 /* Device workspace bytes an operation needs (R: CP rank, P: vector pairs;
@@ -189,6 +190,26 @@ FCS_API fcs_status fcs_sketch_cp(fcs_plan_t plan, int64_t R, const float *const 
                          const float *lambda, float *out, float *spec,
                          void *ws, size_t ws_bytes, void *stream);
 
+/* Kronecker product compression, Section 4.3: the FCS of A (x) B viewed as
+ * the order-4 tensor T[i0, i1, i2, i3] = A[i0, i1] B[i2, i3] (modes of the
+ * plan: 0, 1 index A, 2, 3 index B).  Computed as the linear convolution of
+ * the order-2 sketches of A and B (FCS is a convolution of mode sketches),
+ * each summed exactly in 64-bit fixed point from the float entries (the
+ * largest magnitude of a matrix maps into [2^27, 2^28)), then transformed,
+ * multiplied and inverted in float.
+ *   plan  order-4 plan; (J_0 + J_1 - 1) and (J_2 + J_3 - 1) 64-bit bins must
+ *         fit in LDS (about 20000 bins)
+ *   A     device, float, I_0 x I_1 column-major (vec(A))
+ *   B     device, float, I_2 x I_3 column-major
+ *   out   device, float, D x J~; overwritten (may be NULL if spec is set)
+ *   spec  device, float2, D x fcs_plan_spec_len, or NULL
+ *   ws    device workspace of ws_bytes >= fcs_workspace_bytes(FCS_OP_KRON)
+ * A matrix with a non-finite entry gives a NaN sketch.
+ * Errors: FCS_EINVAL, FCS_ENOMEM, FCS_EUNSUPPORTED, FCS_EDEVICE. */
+FCS_API fcs_status fcs_sketch_kron(fcs_plan_t plan, const float *A, const float *B,
+                           float *out, float *spec, void *ws, size_t ws_bytes,
+                           void *stream);
+
 /* Spectrum of existing sketches (for contractions of dense or COO sketches):
  *   y     device, float, D x J~
  *   spec  device, float2, D x fcs_plan_spec_len; overwritten
@@ -223,6 +244,69 @@ FCS_API fcs_status fcs_contract_free_mode(fcs_plan_t plan, const float *spec,
                                   int32_t free_mode, int64_t P,
                                   const float *const *vecs, double *out,
                                   void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Batched uneven sketches: many CP and Kronecker sketch computations, each
+ * with its own plan (order, sizes, hash lengths, D, seed), run by persistent
+ * kernels (one per FFT size class) that take work tiles from a queue,
+ * longest first; fcs_batch_run can capture all of them into one hipGraph
+ * and replay it.  Results equal those of fcs_sketch_cp / fcs_sketch_kron on
+ * each item alone (up to float summation order).
+ * ------------------------------------------------------------------------ */
+enum { FCS_ITEM_CP = 0, FCS_ITEM_KRON = 1 };
+
+typedef struct {
+    fcs_plan_t plan;          /* bound plan of this item; must outlive the batch */
+    int32_t kind;             /* FCS_ITEM_CP or FCS_ITEM_KRON                   */
+    int64_t R;                /* CP rank >= 0 (ignored for KRON)                */
+    const float *const *U;    /* host array of device pointers: CP: N factors as
+                                 for fcs_sketch_cp; KRON: {A, B} as for
+                                 fcs_sketch_kron (read when the batch is created) */
+    const float *lambda;      /* CP: device, R weights, or NULL for all ones   */
+    float *out;               /* device, D x J~, or NULL if spec is set        */
+    float *spec;              /* device, float2 D x fcs_plan_spec_len, or NULL */
+} fcs_batch_item;
+
+typedef struct {
+    int32_t tile_ffts;        /* target forward FFTs per CP tile (ranks x modes);
+                                 0 = 32                                          */
+    int32_t wg_per_cu[7];     /* persistent workgroups per compute unit for the
+                                 FFT sizes 2^8 .. 2^14; 0 = as many as LDS allows
+                                 (at most 8)                                    */
+} fcs_batch_config;
+
+typedef struct fcs_batch *fcs_batch_t;
+
+/* Host only: validates every item, splits the work into tiles and lays out
+ * the workspace.  cfg may be NULL (defaults).  Output and factor pointers
+ * are captured here.  Errors: FCS_EINVAL, FCS_EUNSUPPORTED. */
+FCS_API fcs_status fcs_batch_create(const fcs_batch_item *items, int64_t count,
+                            const fcs_batch_config *cfg, fcs_batch_t *out);
+
+/* Device workspace bytes (descriptors, tile queues, counters, partial
+ * spectra, Kronecker factor sketches). */
+FCS_API size_t fcs_batch_workspace_bytes(fcs_batch_t batch);
+
+/* Tiles of the batch and the persistent grid of each FFT size class
+ * (grids: 7 entries or NULL). */
+FCS_API fcs_status fcs_batch_info(fcs_batch_t batch, int64_t *tiles, int32_t *grids);
+
+/* Copies the descriptors and tile lists into ws (device, 256-byte aligned,
+ * ws_bytes >= fcs_batch_workspace_bytes) and clears the counters; waits for
+ * the copies (synchronises `stream`).  Call again after moving to another
+ * workspace.  Errors: FCS_EINVAL, FCS_ENOMEM, FCS_EDEVICE. */
+FCS_API fcs_status fcs_batch_prepare(fcs_batch_t batch, void *ws, size_t ws_bytes,
+                             void *stream);
+
+/* Computes every item into its out / spec on `stream`.  use_graph != 0
+ * captures the launches into a hipGraph on the first call (per workspace)
+ * and replays it; 0 launches the class kernels directly.  ws must be the
+ * prepared workspace; runs of one batch must not overlap in time.
+ * Errors: FCS_EINVAL, FCS_ENOMEM, FCS_EUNSUPPORTED, FCS_EDEVICE. */
+FCS_API fcs_status fcs_batch_run(fcs_batch_t batch, void *ws, size_t ws_bytes,
+                         int32_t use_graph, void *stream);
+
+FCS_API fcs_status fcs_batch_destroy(fcs_batch_t batch);
 
 /* Text of a status code (static storage). */
 FCS_API const char *fcs_status_str(fcs_status status);

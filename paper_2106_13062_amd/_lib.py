@@ -18,13 +18,24 @@ U64 = ctypes.c_uint64
 SZ = ctypes.c_size_t
 
 FCS_OK, FCS_EINVAL, FCS_ENOMEM, FCS_EADMIT, FCS_EDEVICE, FCS_EUNSUPPORTED = range(6)
-OP_DENSE, OP_COO, OP_CP, OP_INNER, OP_FREE_MODE, OP_SPECTRUM = range(6)
+OP_DENSE, OP_COO, OP_CP, OP_INNER, OP_FREE_MODE, OP_SPECTRUM, OP_KRON = range(7)
+ITEM_CP, ITEM_KRON = 0, 1
+NCLASS = 7
 MAX_ORDER, MAX_D, MAX_FFT = 8, 64, 16384
 
 
 class PlanDesc(ctypes.Structure):
     _fields_ = [("N", I32), ("I", ctypes.POINTER(I64)), ("J", ctypes.POINTER(I64)),
                 ("D", I32), ("seed", U64), ("L", I64)]
+
+
+class BatchItem(ctypes.Structure):
+    _fields_ = [("plan", P), ("kind", I32), ("R", I64), ("U", ctypes.POINTER(P)), ("lam", P),
+                ("out", P), ("spec", P)]
+
+
+class BatchConfig(ctypes.Structure):
+    _fields_ = [("tile_ffts", I32), ("wg_per_cu", I32 * 7)]
 
 
 # (name, restype, argtypes); every entry point of include/fcs.h
@@ -42,6 +53,14 @@ SIGNATURES = {
     "fcs_sketch_coo": (I32, [P, I64, P, P, P, P, SZ, P]),
     "fcs_sketch_cp": (I32, [P, I64, ctypes.POINTER(P), P, P, P, P, SZ, P]),
     "fcs_sketch_spectrum": (I32, [P, P, P, P, SZ, P]),
+    "fcs_sketch_kron": (I32, [P, P, P, P, P, P, SZ, P]),
+    "fcs_batch_create": (I32, [ctypes.POINTER(BatchItem), I64, ctypes.POINTER(BatchConfig),
+                               ctypes.POINTER(P)]),
+    "fcs_batch_workspace_bytes": (SZ, [P]),
+    "fcs_batch_info": (I32, [P, ctypes.POINTER(I64), ctypes.POINTER(I32)]),
+    "fcs_batch_prepare": (I32, [P, P, SZ, P]),
+    "fcs_batch_run": (I32, [P, P, SZ, I32, P]),
+    "fcs_batch_destroy": (I32, [P]),
     "fcs_contract_inner": (I32, [P, P, P, P, P, P, SZ, P]),
     "fcs_contract_free_mode": (I32, [P, P, I32, I64, ctypes.POINTER(P), P, P, SZ, P]),
     "fcs_status_str": (ctypes.c_char_p, [I32]),

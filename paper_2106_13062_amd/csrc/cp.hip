@@ -21,235 +21,46 @@
 
 #include <algorithm>
 
+#include "cp_tile.h"
 #include "fft.h"
 #include "median.h"
 
 using namespace fcsfft;
+using namespace fcscp;
 
 namespace {
 
-struct SliceArgs {
-    const float2 *twP;
-    const float2 *twL;
-    int L, P, Q, Qh;
-};
-
-// Slice q of the DFT of one mode's count sketch CS_n(u): builds w_q in LDS
-// (natural order, padded).  u is the factor column (I_n floats), the inverse
-// lists give the buckets of h_n.  Each thread writes its own positions.  The
-// loads are issued in batches over the thread's E positions (bucket bounds,
-// then first entries, then factor values) so that their latencies overlap;
-// buckets with more than one entry (rare when J_n >= I_n) finish in a loop.
-template <int P>
-__device__ __forceinline__ void build_cs_slice(float2 *lds, const float *__restrict__ u,
-                                               const int32_t *__restrict__ off,
-                                               const int32_t *__restrict__ ent, int Jn, int q,
-                                               const SliceArgs &s, float scale) {
-    constexpr int T = Shape<P>::T;
-    constexpr int E = Shape<P>::E;
-    const int t = tid_opaque();
-    if (Jn <= P) {
-        // positions t + e*T in groups of G (smaller groups for 1024-thread
-        // workgroups, whose register budget is half)
-        constexpr int G = (T >= 1024) ? E / 4 : E;
-#pragma unroll
-        for (int g0 = 0; g0 < E; g0 += G) {
-            int b0[G], b1[G];
-#pragma unroll
-            for (int g = 0; g < G; ++g) {
-                const int j = t + (g0 + g) * T;
-                const bool in = j < Jn;
-                b0[g] = in ? off[j] : 0;
-                b1[g] = in ? off[j + 1] : 0;
-            }
-            uint32_t e0[G];
-#pragma unroll
-            for (int g = 0; g < G; ++g) e0[g] = (b1[g] > b0[g]) ? (uint32_t)ent[b0[g]] : 0u;
-            float y[G];
-#pragma unroll
-            for (int g = 0; g < G; ++g) {
-                const float v = (b1[g] > b0[g]) ? u[e0[g] & FCS_H_MASK] : 0.f;
-                y[g] = __uint_as_float(__float_as_uint(v) ^ (e0[g] & FCS_S_BIT));
-            }
-#pragma unroll
-            for (int g = 0; g < G; ++g) {
-                for (int k = b0[g] + 1; k < b1[g]; ++k) {
-                    const uint32_t w = (uint32_t)ent[k];
-                    y[g] += __uint_as_float(__float_as_uint(u[w & FCS_H_MASK]) ^ (w & FCS_S_BIT));
-                }
-            }
-#pragma unroll
-            for (int g = 0; g < G; ++g) {
-                const int m = t + (g0 + g) * T;
-                const float ys = y[g] * scale;
-                if (q == 0) {
-                    lds[pad(m)] = make_float2(ys, 0.f);
-                } else {
-                    const float2 w = s.twL[(int)(((int64_t)q * m) % s.L)];
-                    lds[pad(m)] = make_float2(ys * w.x, ys * w.y);
-                }
-            }
-        }
-        return;
-    }
-    // J_n > P: fold the buckets of m, m + P, m + 2P, ... onto position m
-    for (int m = t; m < P; m += T) {
-        float2 acc = make_float2(0.f, 0.f);
-        for (int j = m; j < Jn; j += P) {
-            float y = 0.f;
-            const int c0 = off[j], c1 = off[j + 1];
-            for (int k = c0; k < c1; ++k) {
-                const uint32_t w = (uint32_t)ent[k];
-                y += __uint_as_float(__float_as_uint(u[w & FCS_H_MASK]) ^ (w & FCS_S_BIT));
-            }
-            if (q == 0) {
-                acc.x += y;
-            } else {
-                const float2 w = s.twL[(int)(((int64_t)q * j) % s.L)];
-                acc.x += y * w.x;
-                acc.y += y * w.y;
-            }
-        }
-        lds[pad(m)] = make_float2(acc.x * scale, acc.y * scale);
-    }
-}
-
-// Slice q of the DFT of a dense real sequence y[0..M): w_q in LDS.
-template <int P>
-__device__ __forceinline__ void build_seq_slice(float2 *lds, const float *__restrict__ y, int M, int q,
-                                                const SliceArgs &s) {
-    constexpr int T = Shape<P>::T;
-    for (int m = tid_opaque(); m < P; m += T) {
-        float2 acc = make_float2(0.f, 0.f);
-        for (int j = m; j < M; j += P) {
-            const float v = y[j];
-            if (q == 0) {
-                acc.x += v;
-            } else {
-                const float2 w = s.twL[(int)(((int64_t)q * j) % s.L)];
-                acc.x += v * w.x;
-                acc.y += v * w.y;
-            }
-        }
-        lds[pad(m)] = acc;
-    }
-}
-
-// Real part of the slice-q term of the inverse at position m:
-// c_q Re(exp(+2 pi i q m / L) Z) / L.
-__device__ __forceinline__ float inv_term(const SliceArgs &s, int q, int64_t m, float2 Z) {
-    const float cq = (q == 0 || (2 * q == s.Q)) ? 1.f : 2.f;
-    if (q == 0) return cq * Z.x / (float)s.L;
-    const float2 w = s.twL[(int)(((int64_t)q * m) % s.L)];   // exp(-2 pi i q m / L)
-    return cq * (w.x * Z.x + w.y * Z.y) / (float)s.L;         // Re(conj(w) Z)
-}
-
 // ---------------------------------------------------------------------------
-// CP sketch, forward part: one workgroup per (sketch d, slice q, rank chunk);
-// for every rank r of the chunk the N mode spectra of slice q are formed in
-// LDS, multiplied in registers, weighted by lambda_r and summed; the chunk's
-// partial spectrum goes to the workspace.
+// CP sketch: forward tiles (sketch d, slice q, rank chunk) write partial
+// spectra, one workgroup per sketch then sums and inverts them.  A plan with
+// a single slice and a single chunk inverts inside the forward tile.
 // ---------------------------------------------------------------------------
-struct CpArgs {
-    const float *U[FCS_MAX_ORDER];
-    const float *lambda;
-    int I[FCS_MAX_ORDER];
-    int J[FCS_MAX_ORDER];
-    const int32_t *inv;
-    int64_t ioff[FCS_MAX_ORDER];
-    int64_t iblock;
-    int N, D, R, nchunks, rchunk;
-    SliceArgs s;
-    float2 *partial;        // [D][Qh][nchunks][P]
-};
-
 template <int P>
-__global__ __launch_bounds__(Shape<P>::T) void cp_forward_kernel(CpArgs a) {
+__global__ __launch_bounds__(Shape<P>::T) void cp_forward_kernel(CpDesc c) {
     extern __shared__ float2 lds[];
-    constexpr int E = Shape<P>::E;
-    constexpr int T = Shape<P>::T;
     const int tile = blockIdx.x;
-    const int chunk = tile % a.nchunks;
-    const int q = (tile / a.nchunks) % a.s.Qh;
-    const int d = tile / (a.nchunks * a.s.Qh);
-    const int r0 = chunk * a.rchunk;
-    const int r1 = min(a.R, r0 + a.rchunk);
-    float2 acc[E];
-#pragma unroll
-    for (int e = 0; e < E; ++e) acc[e] = make_float2(0.f, 0.f);
-    const int32_t *invd = a.inv + (int64_t)d * a.iblock;
-    for (int r = r0; r < r1; ++r) {
-        float2 prod[E];
-        const float lam = a.lambda ? a.lambda[r] : 1.0f;
-        for (int n = 0; n < a.N; ++n) {
-            const int32_t *off = invd + a.ioff[n];
-            build_cs_slice<P>(lds, a.U[n] + (int64_t)r * a.I[n], off, off + a.J[n] + 1, a.J[n], q, a.s,
-                              n == 0 ? lam : 1.0f);
-            __syncthreads();
-            float2 v[E];
-            forward<P>(lds, a.s.twP, v);
-#pragma unroll
-            for (int e = 0; e < E; ++e) prod[e] = (n == 0) ? v[e] : cmul(prod[e], v[e]);
-        }
-#pragma unroll
-        for (int e = 0; e < E; ++e) acc[e] = cadd(acc[e], prod[e]);
-    }
-    float2 *dst = a.partial + (((int64_t)d * a.s.Qh + q) * a.nchunks + chunk) * P;
-#pragma unroll
-    for (int e = 0; e < E; ++e) dst[threadIdx.x + e * T] = acc[e];
+    const int chunk = tile % c.nchunks;
+    const int q = (tile / c.nchunks) % c.s.Qh;
+    const int d = tile / (c.nchunks * c.s.Qh);
+    float2 acc[Shape<P>::E];
+    cp_tile<P>(c, d, q, chunk, lds, acc);
+    if (c.nchunks * c.s.Qh == 1)
+        finish_slice<P>(c, d, 0, lds, acc);
+    else
+        store_partial<P>(c, d, q, chunk, acc);
 }
 
-// ---------------------------------------------------------------------------
-// Inverse part: one workgroup per sketch; sums the chunk partials of every
-// slice (fixed order), optionally stores the spectrum, inverts the slices
-// and accumulates y[0..J~) in HBM (each thread owns fixed positions).
-// ---------------------------------------------------------------------------
-struct FinArgs {
-    const float2 *partial;
-    int nchunks;
-    SliceArgs s;
-    float *out;             // D x Jt or null
-    float2 *spec;           // D x (Qh * P) or null
-    int64_t Jt;
-};
-
 template <int P>
-__global__ __launch_bounds__(Shape<P>::T) void cp_finalize_kernel(FinArgs a) {
+__global__ __launch_bounds__(Shape<P>::T) void cp_finalize_kernel(CpDesc c) {
     extern __shared__ float2 lds[];
-    constexpr int E = Shape<P>::E;
-    constexpr int T = Shape<P>::T;
-    const int d = blockIdx.x;
-    for (int q = 0; q < a.s.Qh; ++q) {
-        float2 X[E];
-#pragma unroll
-        for (int e = 0; e < E; ++e) X[e] = make_float2(0.f, 0.f);
-        const float2 *src = a.partial + ((int64_t)d * a.s.Qh + q) * a.nchunks * P + tid_opaque();
-        for (int c = 0; c < a.nchunks; ++c) {
-#pragma unroll
-            for (int e = 0; e < E; ++e) X[e] = cadd(X[e], src[(int64_t)c * P + e * T]);
-        }
-        if (a.spec) {
-            float2 *sp = a.spec + ((int64_t)d * a.s.Qh + q) * P;
-#pragma unroll
-            for (int e = 0; e < E; ++e) sp[threadIdx.x + e * T] = X[e];
-        }
-        if (!a.out) continue;
-        store<P>(lds, X);
-        __syncthreads();
-        float2 Z[E];
-        inverse<P>(lds, a.s.twP, Z);
-        const int tt = tid_opaque();
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const int k = tt + e * T;
-            for (int64_t m = k; m < a.Jt; m += P) {
-                const float t = inv_term(a.s, q, m, Z[e]);
-                float *dst = a.out + (int64_t)d * a.Jt + m;
-                *dst = (q == 0) ? t : *dst + t;
-            }
-        }
-        __syncthreads();
-    }
+    cp_finalize<P>(c, blockIdx.x, lds);
+}
+
+// Kronecker product of two matrices: one workgroup per sketch.
+template <int P>
+__global__ __launch_bounds__(Shape<P>::T) void kron_kernel(CpDesc c) {
+    extern __shared__ float2 lds[];
+    kron_sketch<P>(c, blockIdx.x, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -366,17 +177,6 @@ __global__ __launch_bounds__(256) void median_rows_kernel(const float *est, int6
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
-SliceArgs slice_args(const fcs_plan *p) {
-    SliceArgs s;
-    s.twP = p->twP;
-    s.twL = p->twL;
-    s.L = (int)p->L;
-    s.P = (int)p->P;
-    s.Q = p->Q;
-    s.Qh = p->Qh;
-    return s;
-}
-
 int cp_chunks(const fcs_plan *p, int64_t R) {
     if (R <= 0) return 1;
     const int64_t tiles = (int64_t)p->D * p->Qh;
@@ -393,12 +193,20 @@ void allow_lds_cp(K kernel, size_t bytes) {
 }
 
 template <int P>
-void launch_cp(const CpArgs &ca, const FinArgs &fa, int D, int Qh, hipStream_t s) {
+void launch_cp(const CpDesc &c, hipStream_t s) {
     constexpr size_t lds = Lds<P>::bytes;
     allow_lds_cp(cp_forward_kernel<P>, lds);
     allow_lds_cp(cp_finalize_kernel<P>, lds);
-    hipLaunchKernelGGL(cp_forward_kernel<P>, dim3(D * Qh * ca.nchunks), dim3(Shape<P>::T), lds, s, ca);
-    hipLaunchKernelGGL(cp_finalize_kernel<P>, dim3(D), dim3(Shape<P>::T), lds, s, fa);
+    hipLaunchKernelGGL(cp_forward_kernel<P>, dim3(c.D * c.s.Qh * c.nchunks), dim3(Shape<P>::T), lds, s, c);
+    if (c.s.Qh * c.nchunks > 1)
+        hipLaunchKernelGGL(cp_finalize_kernel<P>, dim3(c.D), dim3(Shape<P>::T), lds, s, c);
+}
+
+template <int P>
+void launch_kron(const CpDesc &c, hipStream_t s) {
+    const size_t lds = cp_lds_bytes(P, c);
+    allow_lds_cp(kron_kernel<P>, lds);
+    hipLaunchKernelGGL(kron_kernel<P>, dim3(c.D), dim3(Shape<P>::T), lds, s, c);
 }
 
 template <int P>
@@ -415,18 +223,6 @@ void launch_free(const FreeArgs &fa, hipStream_t s) {
     hipLaunchKernelGGL(free_mode_kernel<P>, dim3(fa.D * fa.Pn), dim3(Shape<P>::T), lds, s, fa);
 }
 
-#define FCS_DISPATCH_P(P_, CALL)                 \
-    switch (P_) {                                \
-    case 256: { constexpr int PP = 256; CALL; } break;     \
-    case 512: { constexpr int PP = 512; CALL; } break;     \
-    case 1024: { constexpr int PP = 1024; CALL; } break;   \
-    case 2048: { constexpr int PP = 2048; CALL; } break;   \
-    case 4096: { constexpr int PP = 4096; CALL; } break;   \
-    case 8192: { constexpr int PP = 8192; CALL; } break;   \
-    case 16384: { constexpr int PP = 16384; CALL; } break; \
-    default: FCS_FAIL(FCS_EUNSUPPORTED, "FFT size %lld not built", (long long)(P_)); \
-    }
-
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 }  // namespace
@@ -434,7 +230,13 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 size_t fcs_ws_cp(const fcs_plan *p, int64_t R) {
     if (p->P == 0) return 256;
     const int nch = cp_chunks(p, R);
+    if (nch * p->Qh == 1) return 256;     // single tile per sketch: no partials
     return align256((size_t)p->D * p->Qh * nch * p->P * sizeof(float2));
+}
+
+size_t fcs_ws_kron(const fcs_plan *p) {
+    if (p->N != 4) return 256;
+    return align256((size_t)p->D * (p->J[0] + p->J[1] - 1 + p->J[2] + p->J[3] - 1) * sizeof(float));
 }
 
 size_t fcs_ws_spectrum(const fcs_plan *) { return 256; }
@@ -472,31 +274,49 @@ extern "C" fcs_status fcs_sketch_cp(fcs_plan_t p, int64_t R, const float *const 
     const size_t need = fcs_ws_cp(p, R);
     if (!ws || ws_bytes < need) FCS_FAIL(FCS_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, need);
     if (!fcs_aligned(ws, 16)) FCS_FAIL(FCS_EINVAL, "workspace not 16-byte aligned");
-    CpArgs ca{};
-    for (int n = 0; n < p->N; ++n) {
-        ca.U[n] = U[n];
-        ca.I[n] = (int)p->I[n];
-        ca.J[n] = (int)p->J[n];
-        ca.ioff[n] = p->ioff[n];
-    }
-    ca.lambda = lambda;
-    ca.inv = p->inv;
-    ca.iblock = p->iblock;
-    ca.N = p->N;
-    ca.D = p->D;
-    ca.R = (int)R;
-    ca.nchunks = cp_chunks(p, R);
-    ca.rchunk = (int)fcs_ceil_div(R, ca.nchunks);
-    ca.s = slice_args(p);
-    ca.partial = (float2 *)ws;
-    FinArgs fa{};
-    fa.partial = ca.partial;
-    fa.nchunks = ca.nchunks;
-    fa.s = ca.s;
-    fa.out = out;
-    fa.spec = (float2 *)spec;
-    fa.Jt = p->Jt;
-    FCS_DISPATCH_P(p->P, (launch_cp<PP>(ca, fa, p->D, p->Qh, s)));
+    CpDesc c{};
+    desc_from_plan(c, p);
+    c.kind = FCS_DESC_CP;
+    for (int n = 0; n < p->N; ++n) c.U[n] = U[n];
+    c.lambda = lambda;
+    c.R = (int)R;
+    c.nchunks = cp_chunks(p, R);
+    c.rchunk = (int)fcs_ceil_div(R, c.nchunks);
+    c.partial = (float2 *)ws;
+    c.out = out;
+    c.spec = (float2 *)spec;
+    FCS_DISPATCH_FFT(p->P, (launch_cp<PP>(c, s)));
+    FCS_LAUNCH_CHECK();
+    return FCS_OK;
+}
+
+extern "C" fcs_status fcs_sketch_kron(fcs_plan_t p, const float *A, const float *B, float *out, float *spec,
+                                      void *ws, size_t ws_bytes, void *stream) {
+    fcs_clear_error();
+    if (!p || !p->bound) FCS_FAIL(FCS_EINVAL, "plan is null or not bound");
+    if (p->N != 4) FCS_FAIL(FCS_EINVAL, "a Kronecker sketch needs an order-4 plan (N=%d)", p->N);
+    if (p->P == 0) FCS_FAIL(FCS_EUNSUPPORTED, "no transform length fits this plan");
+    if (!A || !B) FCS_FAIL(FCS_EINVAL, "null factor matrix");
+    if (!out && !spec) FCS_FAIL(FCS_EINVAL, "neither out nor spec given");
+    CpDesc c{};
+    desc_from_plan(c, p);
+    c.kind = FCS_DESC_KRON;
+    if (cp_lds_bytes((int)p->P, c) > FCS_LDS_BYTES - 1024)
+        FCS_FAIL(FCS_EUNSUPPORTED, "factor sketches of %d and %d bins exceed LDS", c.J[0] + c.J[1] - 1,
+                 c.J[2] + c.J[3] - 1);
+    const size_t need = fcs_ws_kron(p);
+    if (!ws || ws_bytes < need) FCS_FAIL(FCS_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, need);
+    if (!fcs_aligned(ws, 16)) FCS_FAIL(FCS_EINVAL, "workspace not 16-byte aligned");
+    c.U[0] = A;
+    c.U[1] = B;
+    c.R = 1;
+    c.nchunks = 1;
+    c.rchunk = 1;
+    c.kscratch = (float *)ws;
+    c.out = out;
+    c.spec = (float2 *)spec;
+    hipStream_t s = (hipStream_t)stream;
+    FCS_DISPATCH_FFT(p->P, (launch_kron<PP>(c, s)));
     FCS_LAUNCH_CHECK();
     return FCS_OK;
 }
@@ -515,7 +335,7 @@ extern "C" fcs_status fcs_sketch_spectrum(fcs_plan_t p, const float *y, float *s
     sa.Jt = p->Jt;
     sa.s = slice_args(p);
     hipStream_t s = (hipStream_t)stream;
-    FCS_DISPATCH_P(p->P, (launch_spectrum<PP>(sa, p->D, p->Qh, s)));
+    FCS_DISPATCH_FFT(p->P, (launch_spectrum<PP>(sa, p->D, p->Qh, s)));
     FCS_LAUNCH_CHECK();
     return FCS_OK;
 }
@@ -559,7 +379,7 @@ extern "C" fcs_status fcs_contract_free_mode(fcs_plan_t p, const float *spec, in
     fa.zbuf = (float *)ws;
     fa.est = (float *)((char *)ws + align256((size_t)p->D * Pn * Jmax * 4));
     hipStream_t s = (hipStream_t)stream;
-    FCS_DISPATCH_P(p->P, (launch_free<PP>(fa, s)));
+    FCS_DISPATCH_FFT(p->P, (launch_free<PP>(fa, s)));
     FCS_LAUNCH_CHECK();
     const int64_t rows = Pn * p->I[free_mode];
     const unsigned grid = (unsigned)fcs_ceil_div(rows, 256);

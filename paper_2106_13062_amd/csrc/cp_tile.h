@@ -1,0 +1,410 @@
+// Device building blocks of the CP sketch (Section 3.1 of the paper) shared
+// by the single-plan kernels and the persistent batch kernels:
+//   - count sketches of factor columns built as gathers over the inverse
+//     hash lists, one interleaved slice of the L-point transform at a time
+//     (L = Q * P, P a power of two held in LDS; see cp.hip for the layout),
+//   - one CP work tile: for a rank range, N mode spectra of one slice formed
+//     in LDS, multiplied in registers and summed,
+//   - the inverse: slice partial spectra summed, inverted and accumulated
+//     into y[0..J~),
+//   - the Kronecker product of two matrices (Section 4.3): the order-2 FCS of
+//     each factor matrix and their linear convolution.
+#pragma once
+
+#include "fcs_internal.h"
+#include "fft.h"
+
+// Instantiate CALL with the compile-time FFT size PP equal to P_.
+#define FCS_DISPATCH_FFT(P_, CALL)                           \
+    switch (P_) {                                            \
+    case 256: { constexpr int PP = 256; CALL; } break;       \
+    case 512: { constexpr int PP = 512; CALL; } break;       \
+    case 1024: { constexpr int PP = 1024; CALL; } break;     \
+    case 2048: { constexpr int PP = 2048; CALL; } break;     \
+    case 4096: { constexpr int PP = 4096; CALL; } break;     \
+    case 8192: { constexpr int PP = 8192; CALL; } break;     \
+    case 16384: { constexpr int PP = 16384; CALL; } break;   \
+    default: FCS_FAIL(FCS_EUNSUPPORTED, "FFT size %lld not built", (long long)(P_)); \
+    }
+
+namespace fcscp {
+
+using namespace fcsfft;
+
+struct SliceArgs {
+    const float2 *twP;
+    const float2 *twL;
+    int L, P, Q, Qh;
+};
+
+// Slice q of the DFT of one mode's count sketch CS_n(u): builds w_q in LDS
+// (natural order, padded).  u is the factor column (I_n floats), the inverse
+// lists give the buckets of h_n.  Each thread writes its own positions.  The
+// loads are issued in batches over the thread's E positions (bucket bounds,
+// then first entries, then factor values) so that their latencies overlap;
+// buckets with more than one entry (rare when J_n >= I_n) finish in a loop.
+template <int P>
+__device__ __forceinline__ void build_cs_slice(float2 *lds, const float *__restrict__ u,
+                                               const int32_t *__restrict__ off,
+                                               const int32_t *__restrict__ ent, int Jn, int q,
+                                               const SliceArgs &s, float scale) {
+    constexpr int T = Shape<P>::T;
+    constexpr int E = Shape<P>::E;
+    const int t = tid_opaque();
+    if (Jn <= P) {
+        // positions t + e*T in groups of G (smaller groups for 1024-thread
+        // workgroups, whose register budget is half)
+        constexpr int G = (T >= 1024) ? E / 4 : E;
+#pragma unroll
+        for (int g0 = 0; g0 < E; g0 += G) {
+            int b0[G], b1[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const int j = t + (g0 + g) * T;
+                const bool in = j < Jn;
+                b0[g] = in ? off[j] : 0;
+                b1[g] = in ? off[j + 1] : 0;
+            }
+            uint32_t e0[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) e0[g] = (b1[g] > b0[g]) ? (uint32_t)ent[b0[g]] : 0u;
+            float y[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const float v = (b1[g] > b0[g]) ? u[e0[g] & FCS_H_MASK] : 0.f;
+                y[g] = __uint_as_float(__float_as_uint(v) ^ (e0[g] & FCS_S_BIT));
+            }
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                for (int k = b0[g] + 1; k < b1[g]; ++k) {
+                    const uint32_t w = (uint32_t)ent[k];
+                    y[g] += __uint_as_float(__float_as_uint(u[w & FCS_H_MASK]) ^ (w & FCS_S_BIT));
+                }
+            }
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const int m = t + (g0 + g) * T;
+                const float ys = y[g] * scale;
+                if (q == 0) {
+                    lds[pad(m)] = make_float2(ys, 0.f);
+                } else {
+                    const float2 w = s.twL[(int)(((int64_t)q * m) % s.L)];
+                    lds[pad(m)] = make_float2(ys * w.x, ys * w.y);
+                }
+            }
+        }
+        return;
+    }
+    // J_n > P: fold the buckets of m, m + P, m + 2P, ... onto position m
+    for (int m = t; m < P; m += T) {
+        float2 acc = make_float2(0.f, 0.f);
+        for (int j = m; j < Jn; j += P) {
+            float y = 0.f;
+            const int c0 = off[j], c1 = off[j + 1];
+            for (int k = c0; k < c1; ++k) {
+                const uint32_t w = (uint32_t)ent[k];
+                y += __uint_as_float(__float_as_uint(u[w & FCS_H_MASK]) ^ (w & FCS_S_BIT));
+            }
+            if (q == 0) {
+                acc.x += y;
+            } else {
+                const float2 w = s.twL[(int)(((int64_t)q * j) % s.L)];
+                acc.x += y * w.x;
+                acc.y += y * w.y;
+            }
+        }
+        lds[pad(m)] = make_float2(acc.x * scale, acc.y * scale);
+    }
+}
+
+// Slice q of the DFT of a dense real sequence y[0..M): w_q in LDS.
+template <int P>
+__device__ __forceinline__ void build_seq_slice(float2 *lds, const float *__restrict__ y, int M, int q,
+                                                const SliceArgs &s) {
+    constexpr int T = Shape<P>::T;
+    for (int m = tid_opaque(); m < P; m += T) {
+        float2 acc = make_float2(0.f, 0.f);
+        for (int j = m; j < M; j += P) {
+            const float v = y[j];
+            if (q == 0) {
+                acc.x += v;
+            } else {
+                const float2 w = s.twL[(int)(((int64_t)q * j) % s.L)];
+                acc.x += v * w.x;
+                acc.y += v * w.y;
+            }
+        }
+        lds[pad(m)] = acc;
+    }
+}
+
+// Real part of the slice-q term of the inverse at position m:
+// c_q Re(exp(+2 pi i q m / L) Z) / L.
+__device__ __forceinline__ float inv_term(const SliceArgs &s, int q, int64_t m, float2 Z) {
+    const float cq = (q == 0 || (2 * q == s.Q)) ? 1.f : 2.f;
+    if (q == 0) return cq * Z.x / (float)s.L;
+    const float2 w = s.twL[(int)(((int64_t)q * m) % s.L)];   // exp(-2 pi i q m / L)
+    return cq * (w.x * Z.x + w.y * Z.y) / (float)s.L;         // Re(conj(w) Z)
+}
+
+
+// One CP (or Kronecker) sketch computation as the kernels see it.
+enum { FCS_DESC_CP = 0, FCS_DESC_KRON = 1 };
+
+struct CpDesc {
+    int kind;                        // FCS_DESC_CP or FCS_DESC_KRON
+    int N, D, R;
+    int nchunks, rchunk;             // rank chunks of the forward tiles
+    int I[FCS_MAX_ORDER];
+    int J[FCS_MAX_ORDER];
+    const float *U[FCS_MAX_ORDER];   // CP: factor n column-major (I_n x R); KRON: U[0] = vec(A), U[1] = vec(B)
+    const float *lambda;             // R weights or null
+    const int32_t *inv;              // inverse hash lists, iblock words per sketch
+    int64_t ioff[FCS_MAX_ORDER];
+    int64_t iblock;
+    const uint32_t *tab;             // packed hash words, sumI per sketch
+    int64_t off[FCS_MAX_ORDER];
+    int64_t sumI;
+    SliceArgs s;
+    int64_t Jt;
+    float2 *partial;                 // [D][Qh][nchunks][P] forward partial spectra
+    float *kscratch;                 // KRON: [D][J_0 + J_1 - 1 + J_2 + J_3 - 1] factor sketches
+    float *out;                      // D x Jt or null
+    float2 *spec;                    // D x (Qh * P) or null
+    int cnt_base;                    // batch: first completion counter of this computation
+};
+
+// Forward tile (d, q, rank chunk): sum over the chunk's ranks of
+// lambda_r prod_n F_q(CS_n(U_n(:, r))); thread t returns X[t + e T] in acc.
+template <int P>
+__device__ __forceinline__ void cp_tile(const CpDesc &c, int d, int q, int chunk, float2 *lds,
+                                        float2 (&acc)[Shape<P>::E]) {
+    constexpr int E = Shape<P>::E;
+    const int r0 = chunk * c.rchunk;
+    const int r1 = min(c.R, r0 + c.rchunk);
+#pragma unroll
+    for (int e = 0; e < E; ++e) acc[e] = make_float2(0.f, 0.f);
+    const int32_t *invd = c.inv + (int64_t)d * c.iblock;
+    for (int r = r0; r < r1; ++r) {
+        float2 prod[E];
+        const float lam = c.lambda ? c.lambda[r] : 1.0f;
+        for (int n = 0; n < c.N; ++n) {
+            const int32_t *off = invd + c.ioff[n];
+            build_cs_slice<P>(lds, c.U[n] + (int64_t)r * c.I[n], off, off + c.J[n] + 1, c.J[n], q, c.s,
+                              n == 0 ? lam : 1.0f);
+            __syncthreads();
+            float2 v[E];
+            forward<P>(lds, c.s.twP, v);
+#pragma unroll
+            for (int e = 0; e < E; ++e) prod[e] = (n == 0) ? v[e] : cmul(prod[e], v[e]);
+        }
+#pragma unroll
+        for (int e = 0; e < E; ++e) acc[e] = cadd(acc[e], prod[e]);
+    }
+}
+
+template <int P>
+__device__ __forceinline__ void store_partial(const CpDesc &c, int d, int q, int chunk, const float2 (&acc)[Shape<P>::E]) {
+    constexpr int E = Shape<P>::E;
+    constexpr int T = Shape<P>::T;
+    float2 *dst = c.partial + (((int64_t)d * c.s.Qh + q) * c.nchunks + chunk) * P;
+    const int t = tid_opaque();
+#pragma unroll
+    for (int e = 0; e < E; ++e) dst[t + e * T] = acc[e];
+}
+
+// Slice q of the spectrum of sketch d is complete in X (registers): store it
+// if asked, invert it and add its term to y[0..J~) (q = 0 overwrites).  Each
+// thread owns the same positions for every q, so no synchronisation on y is
+// needed.  Ends with a barrier (lds is reused).
+template <int P>
+__device__ __forceinline__ void finish_slice(const CpDesc &c, int d, int q, float2 *lds,
+                                             const float2 (&X)[Shape<P>::E]) {
+    constexpr int E = Shape<P>::E;
+    constexpr int T = Shape<P>::T;
+    if (c.spec) {
+        float2 *sp = c.spec + ((int64_t)d * c.s.Qh + q) * P;
+        const int t = tid_opaque();
+#pragma unroll
+        for (int e = 0; e < E; ++e) sp[t + e * T] = X[e];
+    }
+    if (!c.out) return;
+    store<P>(lds, X);
+    __syncthreads();
+    float2 Z[E];
+    inverse<P>(lds, c.s.twP, Z);
+    const int tt = tid_opaque();
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int k = tt + e * T;
+        for (int64_t m = k; m < c.Jt; m += P) {
+            const float t = inv_term(c.s, q, m, Z[e]);
+            float *dst = c.out + (int64_t)d * c.Jt + m;
+            *dst = (q == 0) ? t : *dst + t;
+        }
+    }
+    __syncthreads();
+}
+
+// Inverse of sketch d from the forward partials: per slice, the chunk
+// partials are summed in a fixed order, then finish_slice.
+template <int P>
+__device__ __forceinline__ void cp_finalize(const CpDesc &c, int d, float2 *lds) {
+    constexpr int E = Shape<P>::E;
+    constexpr int T = Shape<P>::T;
+    for (int q = 0; q < c.s.Qh; ++q) {
+        float2 X[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) X[e] = make_float2(0.f, 0.f);
+        const float2 *src = c.partial + ((int64_t)d * c.s.Qh + q) * c.nchunks * P + tid_opaque();
+        for (int ch = 0; ch < c.nchunks; ++ch) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) X[e] = cadd(X[e], src[(int64_t)ch * P + e * T]);
+        }
+        finish_slice<P>(c, d, q, lds, X);
+    }
+}
+
+// Order-2 FCS of the I_a x I_b column-major matrix M under the hash words
+// ta (mode a) and tb (mode b) of one sketch: y[h_a(i) + h_b(j)] +=
+// s_a(i) s_b(j) M[i, j] for nb = J_a + J_b - 1 bins, written to y (global).
+// Entries are quantised to integers (the largest magnitude maps into
+// [2^27, 2^28)) and summed exactly in 64-bit LDS bins; lds must hold nb
+// 64-bit words.  A matrix with a non-finite entry gives NaN bins.
+template <int T>
+__device__ __forceinline__ void kron_factor_sketch(const float *__restrict__ M, int Ia, int Ib,
+                                                   const uint32_t *__restrict__ ta,
+                                                   const uint32_t *__restrict__ tb, int nb, float *y,
+                                                   float2 *lds) {
+    unsigned long long *bins = reinterpret_cast<unsigned long long *>(lds);
+    float *red = reinterpret_cast<float *>(lds);
+    const int t = tid_opaque();
+    const int64_t n = (int64_t)Ia * Ib;
+    float m = 0.f;
+    bool bad = false;
+    for (int64_t k = t; k < n; k += T) {
+        const float v = fabsf(M[k]);
+        bad |= !(v <= 3.4e38f);
+        m = fmaxf(m, v);
+    }
+    // workgroup max (non-finite entries flagged separately)
+    m = bad ? -1.f : m;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const float w = __shfl_xor(m, o, 64);
+        m = (m < 0.f || w < 0.f) ? -1.f : fmaxf(m, w);
+    }
+    float M0 = m;       // one wave: every lane holds the maximum already
+    if constexpr (T > 64) {
+        if ((t & 63) == 0) red[t >> 6] = m;
+        __syncthreads();
+        M0 = 0.f;
+        for (int w = 0; w < T / 64; ++w) {
+            const float v = red[w];
+            M0 = (M0 < 0.f || v < 0.f) ? -1.f : fmaxf(M0, v);
+        }
+        __syncthreads();
+    }
+    if (M0 < 0.f) {
+        for (int j = t; j < nb; j += T) y[j] = __builtin_nanf("");
+        return;
+    }
+    int F = 27;
+    if (M0 > 0.f) F = 28 - __builtin_amdgcn_frexp_expf(M0);
+    F = max(-120, min(120, F));
+    const float scale = ldexpf(1.0f, F);
+    for (int j = t; j < nb; j += T) bins[j] = 0ull;
+    __syncthreads();
+    int i = t % Ia, j = t / Ia;
+    const int st_i = T % Ia, st_j = T / Ia;
+    for (int64_t k = t; k < n; k += T) {
+        const uint32_t wa = ta[i], wb = tb[j];
+        const int bin = (int)(wa & FCS_H_MASK) + (int)(wb & FCS_H_MASK);
+        long long qv = (long long)__float2int_rn(M[k] * scale);
+        if ((wa ^ wb) & FCS_S_BIT) qv = -qv;
+        atomicAdd(&bins[bin], (unsigned long long)qv);
+        i += st_i;
+        j += st_j;
+        if (i >= Ia) {
+            i -= Ia;
+            ++j;
+        }
+    }
+    __syncthreads();
+    const float inv = ldexpf(1.0f, -F);
+    for (int b = t; b < nb; b += T) y[b] = (float)(long long)bins[b] * inv;
+    __syncthreads();
+}
+
+// Kronecker product A (x) B as an order-4 tensor (Section 4.3): FCS(A (x) B)
+// is the linear convolution of the order-2 sketches of A (modes 0, 1) and B
+// (modes 2, 3); computed slice by slice as F^-1(F(y_A) F(y_B)).
+template <int P>
+__device__ __forceinline__ void kron_sketch(const CpDesc &c, int d, float2 *lds) {
+    constexpr int E = Shape<P>::E;
+    constexpr int T = Shape<P>::T;
+    const uint32_t *tab = c.tab + (int64_t)d * c.sumI;
+    const int na = c.J[0] + c.J[1] - 1;
+    const int nbb = c.J[2] + c.J[3] - 1;
+    float *ya = c.kscratch + (int64_t)d * (na + nbb);
+    float *yb = ya + na;
+    kron_factor_sketch<T>(c.U[0], c.I[0], c.I[1], tab + c.off[0], tab + c.off[1], na, ya, lds);
+    kron_factor_sketch<T>(c.U[1], c.I[2], c.I[3], tab + c.off[2], tab + c.off[3], nbb, yb, lds);
+    __threadfence_block();
+    __syncthreads();
+    for (int q = 0; q < c.s.Qh; ++q) {
+        build_seq_slice<P>(lds, ya, na, q, c.s);
+        __syncthreads();
+        float2 X[E];
+        forward<P>(lds, c.s.twP, X);
+        build_seq_slice<P>(lds, yb, nbb, q, c.s);
+        __syncthreads();
+        float2 Y[E];
+        forward<P>(lds, c.s.twP, Y);
+#pragma unroll
+        for (int e = 0; e < E; ++e) X[e] = cmul(X[e], Y[e]);
+        finish_slice<P>(c, d, q, lds, X);
+    }
+}
+
+// Plan-derived part of a descriptor (host side).
+inline SliceArgs slice_args(const fcs_plan *p) {
+    SliceArgs s;
+    s.twP = p->twP;
+    s.twL = p->twL;
+    s.L = (int)p->L;
+    s.P = (int)p->P;
+    s.Q = p->Q;
+    s.Qh = p->Qh;
+    return s;
+}
+
+inline void desc_from_plan(CpDesc &c, const fcs_plan *p) {
+    c.N = p->N;
+    c.D = p->D;
+    for (int n = 0; n < p->N; ++n) {
+        c.I[n] = (int)p->I[n];
+        c.J[n] = (int)p->J[n];
+        c.ioff[n] = p->ioff[n];
+        c.off[n] = p->off[n];
+    }
+    c.inv = p->inv;
+    c.iblock = p->iblock;
+    c.tab = p->tab;
+    c.sumI = p->sumI;
+    c.s = slice_args(p);
+    c.Jt = p->Jt;
+}
+
+// LDS bytes a kernel of FFT size P needs for a computation.
+__host__ __device__ inline size_t cp_lds_bytes(int P, const CpDesc &c) {
+    size_t b = (size_t)(P + P / 16) * 8;
+    if (c.kind == FCS_DESC_KRON) {
+        const size_t na = (size_t)(c.J[0] + c.J[1] - 1), nb = (size_t)(c.J[2] + c.J[3] - 1);
+        b = na * 8 > b ? na * 8 : b;
+        b = nb * 8 > b ? nb * 8 : b;
+    }
+    return b;
+}
+
+}  // namespace fcscp

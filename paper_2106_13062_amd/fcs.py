@@ -146,6 +146,26 @@ class Plan:
                                        _stream(stream)))
         return out, spec
 
+    def sketch_kron(self, A: torch.Tensor, B: torch.Tensor, out=None, spec=None, want_out=True,
+                    want_spec=False, ws=None, stream=None):
+        """Kronecker product A (x) B of an order-4 plan: A is I_0 x I_1 and B
+        is I_2 x I_3, each given as a float32 tensor of shape (I_1, I_0)
+        (resp. (I_3, I_2)), i.e. the matrix in column-major order."""
+        if self.N != 4:
+            raise ValueError("a Kronecker sketch needs an order-4 plan")
+        _need(A, torch.float32, "A")
+        _need(B, torch.float32, "B")
+        if A.numel() != self.I[0] * self.I[1] or B.numel() != self.I[2] * self.I[3]:
+            raise ValueError("A must have I_0 * I_1 and B I_2 * I_3 entries")
+        if want_out and out is None:
+            out = torch.empty((self.D, self.Jt), dtype=torch.float32, device=self.device)
+        if want_spec and spec is None:
+            spec = torch.empty((self.D, self.spec_len, 2), dtype=torch.float32, device=self.device)
+        ws, nb = self._ws(ws, C.OP_KRON)
+        C.check(self.lib.fcs_sketch_kron(self._h, _ptr(A), _ptr(B), _ptr(out), _ptr(spec), _ptr(ws), nb,
+                                         _stream(stream)))
+        return out, spec
+
     def spectrum(self, y: torch.Tensor, spec=None, ws=None, stream=None):
         _need(y, torch.float32, "y")
         spec = torch.empty((self.D, self.spec_len, 2), dtype=torch.float32, device=self.device) \
@@ -190,3 +210,97 @@ class Plan:
         C.check(self.lib.fcs_contract_free_mode(self._h, _ptr(spec), int(free_mode), Pn, ptrs, _ptr(out),
                                                 _ptr(ws), nb, _stream(stream)))
         return out
+
+
+class Batch:
+    """Many uneven CP / Kronecker sketch computations run together by the
+    persistent batch kernels (include/fcs.h, fcs_batch_*).
+
+    items: list of dicts with keys
+      plan   a bound Plan (kept alive by the batch)
+      kind   "cp" or "kron"
+      U      CP: list of N float32 (R, I_n) tensors; KRON: [A, B] as for
+             Plan.sketch_kron
+      lam    optional float32 R weights (CP)
+      out    float32 (D, J~) output tensor (allocated when missing)
+      spec   optional float32 (D, spec_len, 2) spectrum output
+    config: optional dict with "tile_ffts" and "wg_per_cu" (7 ints)."""
+
+    def __init__(self, items, config=None, device=None):
+        self.lib = C.load()
+        self.device = torch.device("cuda") if device is None else torch.device(device)
+        self.items = list(items)
+        n = len(self.items)
+        arr = (C.BatchItem * max(n, 1))()
+        self._keep = []
+        for k, it in enumerate(self.items):
+            plan = it["plan"]
+            kind = it.get("kind", "cp")
+            U = it["U"]
+            if kind == "cp":
+                if len(U) != plan.N:
+                    raise ValueError(f"item {k}: need N factors")
+                R = int(U[0].shape[0])
+                for n_, u in enumerate(U):
+                    _need(u, torch.float32, f"item {k} U[{n_}]")
+                    if tuple(u.shape) != (R, plan.I[n_]):
+                        raise ValueError(f"item {k}: U[{n_}] must be R x I_n")
+                kd = C.ITEM_CP
+            elif kind == "kron":
+                if plan.N != 4 or len(U) != 2:
+                    raise ValueError(f"item {k}: a Kronecker item needs an order-4 plan and [A, B]")
+                _need(U[0], torch.float32, f"item {k} A")
+                _need(U[1], torch.float32, f"item {k} B")
+                if U[0].numel() != plan.I[0] * plan.I[1] or U[1].numel() != plan.I[2] * plan.I[3]:
+                    raise ValueError(f"item {k}: factor matrices have the wrong sizes")
+                R = 1
+                kd = C.ITEM_KRON
+            else:
+                raise ValueError(f"item {k}: unknown kind {kind!r}")
+            if it.get("out") is None and it.get("spec") is None:
+                it["out"] = torch.empty((plan.D, plan.Jt), dtype=torch.float32, device=self.device)
+            if it.get("out") is not None:
+                _need(it["out"], torch.float32, f"item {k} out")
+            if it.get("spec") is not None:
+                _need(it["spec"], torch.float32, f"item {k} spec")
+            ptrs = (ctypes.c_void_p * len(U))(*[u.data_ptr() for u in U])
+            self._keep.append((plan, U, ptrs, it.get("lam"), it.get("out"), it.get("spec")))
+            arr[k] = C.BatchItem(plan.handle, kd, R, ctypes.cast(ptrs, ctypes.POINTER(ctypes.c_void_p)),
+                                 _ptr(it.get("lam")), _ptr(it.get("out")), _ptr(it.get("spec")))
+        cfg = None
+        if config:
+            cfg = C.BatchConfig(int(config.get("tile_ffts", 0)),
+                                (ctypes.c_int32 * 7)(*[int(x) for x in config.get("wg_per_cu", [0] * 7)]))
+        h = ctypes.c_void_p()
+        C.check(self.lib.fcs_batch_create(arr, n, None if cfg is None else ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        nbytes = int(self.lib.fcs_batch_workspace_bytes(h))
+        self.ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+        tiles = ctypes.c_int64()
+        grids = (ctypes.c_int32 * 7)()
+        C.check(self.lib.fcs_batch_info(h, ctypes.byref(tiles), grids))
+        self.tiles = tiles.value
+        self.grids = list(grids)
+        self.prepared = False
+
+    def prepare(self, stream=None):
+        C.check(self.lib.fcs_batch_prepare(self._h, _ptr(self.ws), self.ws.numel(), _stream(stream)))
+        self.prepared = True
+
+    def run(self, graph: bool = True, stream=None):
+        if not self.prepared:
+            self.prepare(stream)
+        C.check(self.lib.fcs_batch_run(self._h, _ptr(self.ws), self.ws.numel(), 1 if graph else 0,
+                                       _stream(stream)))
+        return [it.get("out") for it in self.items]
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self.lib.fcs_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
