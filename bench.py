@@ -178,6 +178,187 @@ def coo_workload(args, torch, dev, T):
             "alg_bytes": alg, "achieved_gbs": alg / (ms * 1e-3) / 1e9}
 
 
+def batch_inputs(torch, dev, count):
+    """Instances of the uneven batch (CP, and every 16th a Kronecker pair)
+    with their factors resident on the device."""
+    import synth
+    insts = synth.batch_instances(count)
+    facs = []
+    for ins, F in synth.instance_inputs(insts):
+        # CP: R x I_n rows (column-major factors); KRON: column-major A, B
+        facs.append([torch.from_numpy(m).to(dev).t().contiguous() for m in F])
+    return insts, facs
+
+
+def batch_items(torch, dev, insts, facs, gather_weight=None):
+    """Plans and outputs of every instance; CP transform lengths from the
+    length model with the given gather weight (None: the planner's)."""
+    from paper_2106_13062_amd import Plan
+    from paper_2106_13062_amd.autotune import choose_length
+    items = []
+    for ins, U in zip(insts, facs):
+        if ins.kind == "kron":
+            plan = Plan(ins.I, ins.J, ins.D, ins.hash_seed, L=max(4 * ins.J[0], 256), device=dev)
+        else:
+            L = 0 if gather_weight is None else choose_length(ins.I, ins.J, gather_weight)
+            plan = Plan(ins.I, ins.J, ins.D, ins.hash_seed, L=L, device=dev)
+        items.append({"plan": plan, "kind": ins.kind, "U": U,
+                      "out": torch.empty((ins.D, plan.Jt), dtype=torch.float32, device=dev)})
+    return items
+
+
+def batch_flops(items):
+    """Forward and inverse FFT work of the batch (5 P log2 P per P-point
+    complex transform), the quantity the batch kernels spend their time on."""
+    total = 0.0
+    for it in items:
+        p = it["plan"]
+        Qh = p.Q // 2 + 1
+        per = 5.0 * p.P * np.log2(p.P)
+        if it["kind"] == "kron":
+            total += p.D * Qh * 3 * per
+        else:
+            R = int(it["U"][0].shape[0])
+            total += p.D * Qh * (p.N * R + 1) * per
+    return total
+
+
+def batch_workload(args, torch, dev):
+    """Config of 4096 uneven CP / Kronecker sketches: one instance per
+    launch (eager and graph-captured) against the autotuned persistent batch
+    launch replayed from one hipGraph."""
+    from paper_2106_13062_amd import Batch
+    from paper_2106_13062_amd import _lib as C
+    from paper_2106_13062_amd.autotune import time_batch, tune_batch, tune_lengths
+    t0 = time.perf_counter()
+    insts, facs = batch_inputs(torch, dev, args.batch_count)
+    items = batch_items(torch, dev, insts, facs)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    log(f"batch: {len(items)} instances set up in {setup_s:.1f} s")
+    stream = torch.cuda.current_stream()
+    plain_out = [torch.empty_like(it["out"]) for it in items]
+    wss = []
+    for it in items:
+        p = it["plan"]
+        if it["kind"] == "kron":
+            wss.append(p.workspace(C.OP_KRON))
+        else:
+            wss.append(p.workspace(C.OP_CP, R=int(it["U"][0].shape[0])))
+
+    def plain():
+        for it, o, w in zip(items, plain_out, wss):
+            p = it["plan"]
+            if it["kind"] == "kron":
+                p.sketch_kron(it["U"][0], it["U"][1], out=o, ws=w, stream=stream)
+            else:
+                p.sketch_cp(it["U"], out=o, ws=w, stream=stream)
+
+    plain()
+    torch.cuda.synchronize()
+    reps = max(1, args.batch_reps)
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        plain()
+    torch.cuda.synchronize()
+    plain_eager_ms = (time.perf_counter() - t1) * 1e3 / reps
+    # the same launches captured into one graph: per-instance kernels
+    # without the host's launch loop
+    plain_graph_ms = None
+    try:
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            stream = torch.cuda.current_stream()
+            plain()
+        stream = torch.cuda.current_stream()
+        g.replay()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            g.replay()
+        e1.record(stream)
+        e1.synchronize()
+        plain_graph_ms = e0.elapsed_time(e1) / reps
+        del g
+    except Exception as exc:  # capture not possible: report the eager path only
+        log(f"plain path graph capture failed: {exc}")
+        stream = torch.cuda.current_stream()
+    # the batch with the planner's lengths and default launch configuration
+    bd = Batch(items, device=dev)
+    default_ms = time_batch(bd, runs=reps, warmup=1)
+    bd.close()
+    del bd
+    # autotuned batch (tuning is not part of the timed region): transform
+    # lengths first, then tile size and persistent grid per FFT size class
+    t2 = time.perf_counter()
+    cfg, trials, weight, len_table = None, [], None, []
+    plain_items = items
+    if args.tune:
+        weight, items, len_table = tune_lengths(lambda w: batch_items(torch, dev, insts, facs, w),
+                                                device=dev, log=log)
+        cfg, trials = tune_batch(items, runs=2, warmup=1, device=dev, log=log)
+    tune_s = time.perf_counter() - t2
+    b = Batch(items, config=cfg, device=dev)
+    batch_ms = time_batch(b, runs=reps, warmup=1)
+    torch.cuda.synchronize()
+    # the one-instance path on the tuned transform lengths as well
+    plain_tuned_ms = None
+    if items is not plain_items:
+        tuned_out = [torch.empty_like(it["out"]) for it in items]
+        twss = [it["plan"].workspace(C.OP_KRON) if it["kind"] == "kron"
+                else it["plan"].workspace(C.OP_CP, R=int(it["U"][0].shape[0])) for it in items]
+
+        def plain_tuned():
+            for it, o, w in zip(items, tuned_out, twss):
+                p = it["plan"]
+                if it["kind"] == "kron":
+                    p.sketch_kron(it["U"][0], it["U"][1], out=o, ws=w, stream=stream)
+                else:
+                    p.sketch_cp(it["U"], out=o, ws=w, stream=stream)
+
+        plain_tuned()
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        for _ in range(reps):
+            plain_tuned()
+        torch.cuda.synchronize()
+        plain_tuned_ms = (time.perf_counter() - t3) * 1e3 / reps
+        del tuned_out, twss
+    # every batched sketch against its one-instance result
+    worst = 0.0
+    for it, o in zip(items, plain_out):
+        a = it["out"].double()
+        r = o.double()
+        nr = torch.linalg.vector_norm(r).item()
+        err = torch.linalg.vector_norm(a - r).item() / nr if nr > 0 else torch.linalg.vector_norm(a).item()
+        worst = max(worst, err)
+    n = len(items)
+    nsk = sum(it["plan"].D for it in items)
+    flops = batch_flops(items)
+    plain_flops = batch_flops(plain_items)
+    base_ms = plain_graph_ms if plain_graph_ms is not None else plain_eager_ms
+    if plain_tuned_ms is not None:
+        base_ms = min(base_ms, plain_tuned_ms)
+    res = {"workload": f"batch{n}: uneven CP (N 3-5, I_n log-uniform [32,4096], R 1-256, J_n 2^8-2^13), "
+                       "every 16th a 256x256 Kronecker pair, D=1",
+           "instances": n, "kron": sum(1 for i in insts if i.kind == "kron"), "tiles": b.tiles,
+           "plain_eager_ms": plain_eager_ms, "plain_graph_ms": plain_graph_ms,
+           "plain_tuned_lengths_ms": plain_tuned_ms,
+           "batched_ms": batch_ms, "batched_default_cfg_ms": default_ms,
+           "sketches_per_s_batched": nsk / (batch_ms * 1e-3),
+           "sketches_per_s_plain": nsk / (base_ms * 1e-3),
+           "speedup_vs_plain": base_ms / batch_ms,
+           "speedup_vs_plain_eager": plain_eager_ms / batch_ms,
+           "fft_tflops_batched": flops / (batch_ms * 1e-3) / 1e12,
+           "fft_tflop_batched": flops / 1e12, "fft_tflop_plain": plain_flops / 1e12,
+           "frac_fp32_peak": flops / (batch_ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS,
+           "max_rel_err_vs_plain": worst, "tuned_config": cfg, "tuned_gather_weight": weight,
+           "length_trials": len_table, "tune_s": tune_s, "tune_trials": len(trials), "setup_s": setup_s}
+    b.close()
+    return res
+
+
 def copy_calibration(torch, dev, nbytes=1 << 30, reps=5):
     """A plain device-to-device copy of known size, for scaling the
     FETCH_SIZE / WRITE_SIZE counters of the profiled kernels."""
@@ -198,9 +379,12 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=1 << 19,
                     help="rows of the tensor the CPU oracle sketches")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "dense1024_traffic.json"))
-    ap.add_argument("--mode", default="full", choices=["full", "dense", "copy"],
+    ap.add_argument("--mode", default="full", choices=["full", "dense", "batch", "copy"],
                     help="full: headline + secondary workloads; dense: headline only; "
-                         "copy: plain copy kernel for counter calibration")
+                         "batch: the uneven batch only; copy: plain copy kernel for counter calibration")
+    ap.add_argument("--batch-count", type=int, default=4096, help="instances of the uneven batch")
+    ap.add_argument("--batch-reps", type=int, default=3, help="timed passes of each batch path")
+    ap.add_argument("--no-tune", dest="tune", action="store_false", help="skip the batch autotuner")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -216,6 +400,9 @@ def main():
     if args.mode == "copy":
         copy_calibration(torch, dev)
         return
+    if args.mode == "batch":
+        print(json.dumps({"batch": batch_workload(args, torch, dev)}), flush=True)
+        return
     cfg, res, cpu, T = dense_workload(args, torch, dev)
     secondary = {}
     if args.mode == "full":
@@ -226,6 +413,10 @@ def main():
         secondary["cp10k"] = cp_workload(args, torch, dev, synth.CP10K, pairs=synth.CP10K.pairs)
         log("secondary: coo")
         secondary["coo"] = coo_workload(args, torch, dev, T)
+        del T
+        T = None
+        log("secondary: uneven batch")
+        secondary["batch"] = batch_workload(args, torch, dev)
     del T
     traffic = None
     if os.path.exists(args.traffic_json):

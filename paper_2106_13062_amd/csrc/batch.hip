@@ -9,11 +9,13 @@
 // from a queue (one atomic counter) in decreasing order of estimated cost,
 // so long tiles start first and short ones fill the tail.
 //
-// Completion.  A CP forward tile writes its partial spectrum, releases it
-// (device-scope fence) and counts itself on the (computation, d) counter;
-// the workgroup that completes the count acquires the partials and runs the
-// inverse for that sketch.  A computation with a single tile per sketch
-// inverts in place.  Counters and queue heads are reset by the kernels
+// Completion.  A CP forward tile of several rank chunks writes its partial
+// spectrum, releases it (device-scope fence) and counts itself on the
+// counter of its slice (d, q); the workgroup that completes the count
+// acquires the partials and inverts that slice (a single chunk inverts in
+// place).  With several slices, each slice writes its term of y to a slice
+// row and counts itself on the counter of sketch d; the last one sums the
+// rows in slice order.  Counters and queue heads are reset by the kernels
 // themselves (the last finisher), so a captured graph replays without any
 // memset node.
 #include "fcs_internal.h"
@@ -78,23 +80,32 @@ __device__ __forceinline__ void batch_tile(const BatchArgs &a, int t, float2 *ld
     }
     const int q = __builtin_amdgcn_readfirstlane(tl.q);
     const int chunk = __builtin_amdgcn_readfirstlane(tl.chunk);
+    const int nch = __builtin_amdgcn_readfirstlane(c.nchunks);
+    const int Qh = __builtin_amdgcn_readfirstlane(c.s.Qh);
     float2 acc[Shape<P>::E];
     cp_tile<P>(c, d, q, chunk, lds, acc);
-    const int ntd = __builtin_amdgcn_readfirstlane(c.s.Qh * c.nchunks);
-    if (ntd == 1) {
-        finish_slice<P>(c, d, 0, lds, acc);
-        return;
-    }
-    store_partial<P>(c, d, q, chunk, acc);
-    int *cnt = a.cnt + c.cnt_base + d;
-    __threadfence();                     // release this tile's partial spectrum
-    __syncthreads();
-    const int prev = wg_atomic_ticket<P>(cnt, slot);
-    if (prev == ntd - 1) {
-        __threadfence();                 // acquire the other tiles' partials
-        cp_finalize<P>(c, d, lds);
+    if (nch == 1) {
+        finish_slice<P>(c, d, q, lds, acc, slice_dst(c, d, q), false);
+    } else {
+        // the last chunk of slice (d, q) to finish inverts the slice
+        store_partial<P>(c, d, q, chunk, acc);
+        int *cnt = a.cnt + c.cnt_slice + d * Qh + q;
+        __threadfence();                 // release this tile's partial spectrum
+        __syncthreads();
+        if (wg_atomic_ticket<P>(cnt, slot) != nch - 1) return;
+        __threadfence();                 // acquire the other chunks' partials
+        slice_from_partials<P>(c, d, q, lds);
         atomicExch(cnt, 0);              // ready for the next run (every lane stores 0)
     }
+    if (Qh == 1 || !c.out) return;
+    // the last slice of sketch d to finish sums the slice terms
+    int *cnt = a.cnt + c.cnt_sketch + d;
+    __threadfence();
+    __syncthreads();
+    if (wg_atomic_ticket<P>(cnt, slot) != Qh - 1) return;
+    __threadfence();
+    sum_slices<Shape<P>::T>(c, d);
+    atomicExch(cnt, 0);
 }
 
 template <int P>
@@ -119,9 +130,7 @@ __global__ __launch_bounds__(Shape<P>::T) void batch_kernel(BatchArgs a) {
 
 template <typename K>
 void allow_lds_batch(K kernel, size_t bytes) {
-    if (bytes > 65536)
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    fcs_allow_lds(reinterpret_cast<const void *>(kernel), bytes);
 }
 
 template <int P>
@@ -149,7 +158,7 @@ struct fcs_batch {
         int grid = 0;
     };
     std::vector<CpDesc> desc;            // device pointers patched at prepare
-    std::vector<size_t> part_off, kscr_off;
+    std::vector<size_t> part_off, ytmp_off, kscr_off;
     std::vector<int> zero_items;         // CP items of rank 0
     Cls cls[NCLASS];
     size_t desc_off = 0, ctr_off = 0, total = 0;
@@ -255,9 +264,8 @@ extern "C" fcs_status fcs_batch_create(const fcs_batch_item *items, int64_t coun
         desc_from_plan(c, p);
         c.out = it.out;
         c.spec = reinterpret_cast<float2 *>(it.spec);
-        c.cnt_base = 0;
         const double lg = std::log2((double)p->P);
-        size_t part = 0, kscr = 0;
+        size_t part = 0, ytmp = 0, kscr = 0;
         if (it.kind == FCS_ITEM_KRON) {
             if (p->N != 4) return fail((fcs_set_error("item %lld: Kronecker item needs N=4", (long long)i), FCS_EINVAL));
             if (!it.U[0] || !it.U[1]) return fail((fcs_set_error("item %lld: null factor matrix", (long long)i), FCS_EINVAL));
@@ -293,11 +301,15 @@ extern "C" fcs_status fcs_batch_create(const fcs_batch_item *items, int64_t coun
                 c.nchunks = (int)fcs_ceil_div(it.R, c.rchunk);
                 double per_rank = 0.0;
                 for (int n = 0; n < p->N; ++n) per_rank += p->P * lg + 4.0 * std::max<int64_t>(p->I[n], p->P);
-                const int ntd = p->Qh * c.nchunks;
-                if (ntd > 1) {
-                    c.cnt_base = b->nctr;
-                    b->nctr += p->D;
+                if (c.nchunks > 1) {
+                    c.cnt_slice = b->nctr;
+                    b->nctr += p->D * p->Qh;
                     part = (size_t)p->D * p->Qh * c.nchunks * p->P * sizeof(float2);
+                }
+                if (p->Qh > 1 && it.out) {
+                    c.cnt_sketch = b->nctr;
+                    b->nctr += p->D;
+                    ytmp = (size_t)p->D * p->Qh * p->Jt * sizeof(float);
                 }
                 for (int d = 0; d < p->D; ++d)
                     for (int q = 0; q < p->Qh; ++q)
@@ -314,6 +326,7 @@ extern "C" fcs_status fcs_batch_create(const fcs_batch_item *items, int64_t coun
         b->cls[ci].lds = std::max(b->cls[ci].lds, cp_lds_bytes((int)p->P, c));
         b->desc.push_back(c);
         b->part_off.push_back(part);
+        b->ytmp_off.push_back(ytmp);
         b->kscr_off.push_back(kscr);
     }
     // costliest tiles first in every class
@@ -342,9 +355,11 @@ extern "C" fcs_status fcs_batch_create(const fcs_batch_item *items, int64_t coun
     b->ctr_off = cur;
     cur = align256(cur + (size_t)(2 * NCLASS + b->nctr) * sizeof(int));
     for (size_t i = 0; i < b->desc.size(); ++i) {
-        const size_t po = b->part_off[i], ko = b->kscr_off[i];
+        const size_t po = b->part_off[i], yo = b->ytmp_off[i], ko = b->kscr_off[i];
         b->part_off[i] = po ? cur : 0;
         cur = align256(cur + po);
+        b->ytmp_off[i] = yo ? cur : 0;
+        cur = align256(cur + yo);
         b->kscr_off[i] = ko ? cur : 0;
         cur = align256(cur + ko);
     }
@@ -373,6 +388,7 @@ extern "C" fcs_status fcs_batch_prepare(fcs_batch_t b, void *ws, size_t ws_bytes
     char *w = static_cast<char *>(ws);
     for (size_t i = 0; i < b->desc.size(); ++i) {
         b->desc[i].partial = b->part_off[i] ? reinterpret_cast<float2 *>(w + b->part_off[i]) : nullptr;
+        b->desc[i].ytmp = b->ytmp_off[i] ? reinterpret_cast<float *>(w + b->ytmp_off[i]) : nullptr;
         b->desc[i].kscratch = b->kscr_off[i] ? reinterpret_cast<float *>(w + b->kscr_off[i]) : nullptr;
     }
     if (!b->desc.empty())

@@ -44,16 +44,29 @@ __global__ __launch_bounds__(Shape<P>::T) void cp_forward_kernel(CpDesc c) {
     const int d = tile / (c.nchunks * c.s.Qh);
     float2 acc[Shape<P>::E];
     cp_tile<P>(c, d, q, chunk, lds, acc);
-    if (c.nchunks * c.s.Qh == 1)
-        finish_slice<P>(c, d, 0, lds, acc);
+    if (c.nchunks == 1)
+        finish_slice<P>(c, d, q, lds, acc, slice_dst(c, d, q), false);
     else
         store_partial<P>(c, d, q, chunk, acc);
 }
 
+// One workgroup per (sketch, slice): sums the chunk partials and inverts.
 template <int P>
 __global__ __launch_bounds__(Shape<P>::T) void cp_finalize_kernel(CpDesc c) {
     extern __shared__ float2 lds[];
-    cp_finalize<P>(c, blockIdx.x, lds);
+    slice_from_partials<P>(c, blockIdx.x / c.s.Qh, blockIdx.x % c.s.Qh, lds);
+}
+
+// y_d = sum of the slice terms, in slice order.
+__global__ __launch_bounds__(256) void sum_slices_kernel(CpDesc c) {
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= (int64_t)c.D * c.Jt) return;
+    const int d = (int)(k / c.Jt);
+    const int64_t m = k - (int64_t)d * c.Jt;
+    const float *src = c.ytmp + (int64_t)d * c.s.Qh * c.Jt + m;
+    float v = 0.f;
+    for (int q = 0; q < c.s.Qh; ++q) v += src[(int64_t)q * c.Jt];
+    c.out[k] = v;
 }
 
 // Kronecker product of two matrices: one workgroup per sketch.
@@ -146,8 +159,9 @@ __global__ __launch_bounds__(Shape<P>::T) void free_mode_kernel(FreeArgs a) {
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int k = tt + e * T;
+            InvTerms it(a.s, q, k, Z[e]);
             for (int m = k; m < Jf; m += P) {
-                const float t = inv_term(a.s, q, m, Z[e]);
+                const float t = it.next();
                 z[m] = (q == 0) ? t : z[m] + t;
             }
         }
@@ -187,9 +201,7 @@ int cp_chunks(const fcs_plan *p, int64_t R) {
 
 template <typename K>
 void allow_lds_cp(K kernel, size_t bytes) {
-    if (bytes > 65536)
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    fcs_allow_lds(reinterpret_cast<const void *>(kernel), bytes);
 }
 
 template <int P>
@@ -198,8 +210,11 @@ void launch_cp(const CpDesc &c, hipStream_t s) {
     allow_lds_cp(cp_forward_kernel<P>, lds);
     allow_lds_cp(cp_finalize_kernel<P>, lds);
     hipLaunchKernelGGL(cp_forward_kernel<P>, dim3(c.D * c.s.Qh * c.nchunks), dim3(Shape<P>::T), lds, s, c);
-    if (c.s.Qh * c.nchunks > 1)
-        hipLaunchKernelGGL(cp_finalize_kernel<P>, dim3(c.D), dim3(Shape<P>::T), lds, s, c);
+    if (c.nchunks > 1)
+        hipLaunchKernelGGL(cp_finalize_kernel<P>, dim3(c.D * c.s.Qh), dim3(Shape<P>::T), lds, s, c);
+    if (c.s.Qh > 1 && c.out)
+        hipLaunchKernelGGL(sum_slices_kernel, dim3((unsigned)fcs_ceil_div((int64_t)c.D * c.Jt, 256)), dim3(256), 0,
+                           s, c);
 }
 
 template <int P>
@@ -227,11 +242,20 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 }  // namespace
 
+// CP workspace: chunk partial spectra (several chunks) and slice terms
+// (several slices)
+static size_t cp_partial_bytes(const fcs_plan *p, int nch) {
+    return nch > 1 ? align256((size_t)p->D * p->Qh * nch * p->P * sizeof(float2)) : 0;
+}
+
+static size_t cp_ytmp_bytes(const fcs_plan *p) {
+    return p->Qh > 1 ? align256((size_t)p->D * p->Qh * p->Jt * sizeof(float)) : 0;
+}
+
 size_t fcs_ws_cp(const fcs_plan *p, int64_t R) {
     if (p->P == 0) return 256;
     const int nch = cp_chunks(p, R);
-    if (nch * p->Qh == 1) return 256;     // single tile per sketch: no partials
-    return align256((size_t)p->D * p->Qh * nch * p->P * sizeof(float2));
+    return std::max<size_t>(256, cp_partial_bytes(p, nch) + cp_ytmp_bytes(p));
 }
 
 size_t fcs_ws_kron(const fcs_plan *p) {
@@ -283,6 +307,7 @@ extern "C" fcs_status fcs_sketch_cp(fcs_plan_t p, int64_t R, const float *const 
     c.nchunks = cp_chunks(p, R);
     c.rchunk = (int)fcs_ceil_div(R, c.nchunks);
     c.partial = (float2 *)ws;
+    c.ytmp = (float *)((char *)ws + cp_partial_bytes(p, c.nchunks));
     c.out = out;
     c.spec = (float2 *)spec;
     FCS_DISPATCH_FFT(p->P, (launch_cp<PP>(c, s)));

@@ -88,16 +88,20 @@ __device__ __forceinline__ void build_cs_slice(float2 *lds, const float *__restr
                 if (q == 0) {
                     lds[pad(m)] = make_float2(ys, 0.f);
                 } else {
-                    const float2 w = s.twL[(int)(((int64_t)q * m) % s.L)];
+                    const float2 w = s.twL[q * m];     // q m < Q P = L
                     lds[pad(m)] = make_float2(ys * w.x, ys * w.y);
                 }
             }
         }
         return;
     }
-    // J_n > P: fold the buckets of m, m + P, m + 2P, ... onto position m
+    // J_n > P: fold the buckets of m, m + P, m + 2P, ... onto position m.
+    // exp(-2 pi i q (m + tP) / L) = exp(-2 pi i q m / L) exp(-2 pi i q t / Q):
+    // the fold sums with the Q-th roots (index q t mod Q, kept incrementally)
+    // and applies the position twist once.
     for (int m = t; m < P; m += T) {
         float2 acc = make_float2(0.f, 0.f);
+        int qt = 0;
         for (int j = m; j < Jn; j += P) {
             float y = 0.f;
             const int c0 = off[j], c1 = off[j + 1];
@@ -108,46 +112,72 @@ __device__ __forceinline__ void build_cs_slice(float2 *lds, const float *__restr
             if (q == 0) {
                 acc.x += y;
             } else {
-                const float2 w = s.twL[(int)(((int64_t)q * j) % s.L)];
+                const float2 w = s.twL[qt * P];
                 acc.x += y * w.x;
                 acc.y += y * w.y;
+                qt += q;
+                if (qt >= s.Q) qt -= s.Q;
             }
         }
+        if (q != 0) acc = cmul(acc, s.twL[q * m]);
         lds[pad(m)] = make_float2(acc.x * scale, acc.y * scale);
     }
 }
 
-// Slice q of the DFT of a dense real sequence y[0..M): w_q in LDS.
+// Slice q of the DFT of a dense real sequence y[0..M): w_q in LDS (same
+// factorised twist as the fold above).
 template <int P>
 __device__ __forceinline__ void build_seq_slice(float2 *lds, const float *__restrict__ y, int M, int q,
                                                 const SliceArgs &s) {
     constexpr int T = Shape<P>::T;
     for (int m = tid_opaque(); m < P; m += T) {
         float2 acc = make_float2(0.f, 0.f);
+        int qt = 0;
         for (int j = m; j < M; j += P) {
             const float v = y[j];
             if (q == 0) {
                 acc.x += v;
             } else {
-                const float2 w = s.twL[(int)(((int64_t)q * j) % s.L)];
+                const float2 w = s.twL[qt * P];
                 acc.x += v * w.x;
                 acc.y += v * w.y;
+                qt += q;
+                if (qt >= s.Q) qt -= s.Q;
             }
         }
+        if (q != 0) acc = cmul(acc, s.twL[q * m]);
         lds[pad(m)] = acc;
     }
 }
 
-// Real part of the slice-q term of the inverse at position m:
-// c_q Re(exp(+2 pi i q m / L) Z) / L.
-__device__ __forceinline__ float inv_term(const SliceArgs &s, int q, int64_t m, float2 Z) {
-    const float cq = (q == 0 || (2 * q == s.Q)) ? 1.f : 2.f;
-    if (q == 0) return cq * Z.x / (float)s.L;
-    const float2 w = s.twL[(int)(((int64_t)q * m) % s.L)];   // exp(-2 pi i q m / L)
-    return cq * (w.x * Z.x + w.y * Z.y) / (float)s.L;         // Re(conj(w) Z)
-}
-
-
+// Slice-q terms of the inverse at the positions m = k + tP (t = 0, 1, ...)
+// of thread position k < P: c_q Re(exp(+2 pi i q m / L) Z) / L with
+// exp(+2 pi i q m / L) = exp(+2 pi i q k / L) exp(+2 pi i q t / Q).
+struct InvTerms {
+    float2 v;        // c_q conj(w_L^{qk}) Z / L
+    int q, qt, Q, P;
+    const float2 *twL;
+    __device__ __forceinline__ InvTerms(const SliceArgs &s, int q_, int k, float2 Z) {
+        const float cq = (q_ == 0 || (2 * q_ == s.Q)) ? 1.f : 2.f;
+        const float sc = cq / (float)s.L;
+        q = q_;
+        qt = 0;
+        Q = s.Q;
+        P = s.P;
+        twL = s.twL;
+        v = (q_ == 0) ? Z : cmulc(Z, s.twL[q_ * k]);
+        v.x *= sc;
+        v.y *= sc;
+    }
+    // term of the next position k + tP (t = 0, 1, ... in order)
+    __device__ __forceinline__ float next() {
+        if (q == 0) return v.x;
+        const float2 w = twL[qt * P];      // exp(-2 pi i q t / Q)
+        qt += q;
+        if (qt >= Q) qt -= Q;
+        return w.x * v.x + w.y * v.y;      // Re(conj(w) v)
+    }
+};
 // One CP (or Kronecker) sketch computation as the kernels see it.
 enum { FCS_DESC_CP = 0, FCS_DESC_KRON = 1 };
 
@@ -167,11 +197,13 @@ struct CpDesc {
     int64_t sumI;
     SliceArgs s;
     int64_t Jt;
-    float2 *partial;                 // [D][Qh][nchunks][P] forward partial spectra
+    float2 *partial;                 // [D][Qh][nchunks][P] forward partial spectra (nchunks > 1)
+    float *ytmp;                     // [D][Qh][Jt] inverse term of every slice (Qh > 1)
     float *kscratch;                 // KRON: [D][J_0 + J_1 - 1 + J_2 + J_3 - 1] factor sketches
     float *out;                      // D x Jt or null
     float2 *spec;                    // D x (Qh * P) or null
-    int cnt_base;                    // batch: first completion counter of this computation
+    int cnt_slice;                   // batch: first (d, q) chunk counter (nchunks > 1)
+    int cnt_sketch;                  // batch: first per-d slice counter (Qh > 1)
 };
 
 // Forward tile (d, q, rank chunk): sum over the chunk's ranks of
@@ -214,12 +246,12 @@ __device__ __forceinline__ void store_partial(const CpDesc &c, int d, int q, int
 }
 
 // Slice q of the spectrum of sketch d is complete in X (registers): store it
-// if asked, invert it and add its term to y[0..J~) (q = 0 overwrites).  Each
-// thread owns the same positions for every q, so no synchronisation on y is
-// needed.  Ends with a barrier (lds is reused).
+// if asked, invert it and write its term of y[0..J~) to dst (accumulate:
+// add to what dst holds).  Each thread owns the same positions for every q.
+// Ends with a barrier (lds is reused).
 template <int P>
 __device__ __forceinline__ void finish_slice(const CpDesc &c, int d, int q, float2 *lds,
-                                             const float2 (&X)[Shape<P>::E]) {
+                                             const float2 (&X)[Shape<P>::E], float *dst, bool accumulate) {
     constexpr int E = Shape<P>::E;
     constexpr int T = Shape<P>::T;
     if (c.spec) {
@@ -228,7 +260,7 @@ __device__ __forceinline__ void finish_slice(const CpDesc &c, int d, int q, floa
 #pragma unroll
         for (int e = 0; e < E; ++e) sp[t + e * T] = X[e];
     }
-    if (!c.out) return;
+    if (!dst) return;
     store<P>(lds, X);
     __syncthreads();
     float2 Z[E];
@@ -237,31 +269,49 @@ __device__ __forceinline__ void finish_slice(const CpDesc &c, int d, int q, floa
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int k = tt + e * T;
+        InvTerms it(c.s, q, k, Z[e]);
         for (int64_t m = k; m < c.Jt; m += P) {
-            const float t = inv_term(c.s, q, m, Z[e]);
-            float *dst = c.out + (int64_t)d * c.Jt + m;
-            *dst = (q == 0) ? t : *dst + t;
+            const float t = it.next();
+            dst[m] = accumulate ? dst[m] + t : t;
         }
     }
     __syncthreads();
 }
 
-// Inverse of sketch d from the forward partials: per slice, the chunk
-// partials are summed in a fixed order, then finish_slice.
+// Where the inverse term of slice q of sketch d goes: straight to the
+// output when there is one slice, else to the slice's row of ytmp.
+__device__ __forceinline__ float *slice_dst(const CpDesc &c, int d, int q) {
+    if (!c.out) return nullptr;
+    if (c.s.Qh == 1) return c.out + (int64_t)d * c.Jt;
+    return c.ytmp + ((int64_t)d * c.s.Qh + q) * c.Jt;
+}
+
+// Slice q of sketch d from its chunk partials (summed in a fixed order).
 template <int P>
-__device__ __forceinline__ void cp_finalize(const CpDesc &c, int d, float2 *lds) {
+__device__ __forceinline__ void slice_from_partials(const CpDesc &c, int d, int q, float2 *lds) {
     constexpr int E = Shape<P>::E;
     constexpr int T = Shape<P>::T;
-    for (int q = 0; q < c.s.Qh; ++q) {
-        float2 X[E];
+    float2 X[E];
 #pragma unroll
-        for (int e = 0; e < E; ++e) X[e] = make_float2(0.f, 0.f);
-        const float2 *src = c.partial + ((int64_t)d * c.s.Qh + q) * c.nchunks * P + tid_opaque();
-        for (int ch = 0; ch < c.nchunks; ++ch) {
+    for (int e = 0; e < E; ++e) X[e] = make_float2(0.f, 0.f);
+    const float2 *src = c.partial + ((int64_t)d * c.s.Qh + q) * c.nchunks * P + tid_opaque();
+    for (int ch = 0; ch < c.nchunks; ++ch) {
 #pragma unroll
-            for (int e = 0; e < E; ++e) X[e] = cadd(X[e], src[(int64_t)ch * P + e * T]);
-        }
-        finish_slice<P>(c, d, q, lds, X);
+        for (int e = 0; e < E; ++e) X[e] = cadd(X[e], src[(int64_t)ch * P + e * T]);
+    }
+    finish_slice<P>(c, d, q, lds, X, slice_dst(c, d, q), false);
+}
+
+// y_d = sum over slices of their terms (fixed order), threads over positions.
+template <int T>
+__device__ __forceinline__ void sum_slices(const CpDesc &c, int d) {
+    if (!c.out) return;
+    const float *src = c.ytmp + (int64_t)d * c.s.Qh * c.Jt;
+    float *dst = c.out + (int64_t)d * c.Jt;
+    for (int64_t m = tid_opaque(); m < c.Jt; m += T) {
+        float v = 0.f;
+        for (int q = 0; q < c.s.Qh; ++q) v += src[(int64_t)q * c.Jt + m];
+        dst[m] = v;
     }
 }
 
@@ -363,7 +413,7 @@ __device__ __forceinline__ void kron_sketch(const CpDesc &c, int d, float2 *lds)
         forward<P>(lds, c.s.twP, Y);
 #pragma unroll
         for (int e = 0; e < E; ++e) X[e] = cmul(X[e], Y[e]);
-        finish_slice<P>(c, d, q, lds, X);
+        finish_slice<P>(c, d, q, lds, X, c.out ? c.out + (int64_t)d * c.Jt : nullptr, q > 0);
     }
 }
 

@@ -78,6 +78,10 @@ static inline int64_t fcs_ceil_div(int64_t a, int64_t b) { return (a + b - 1) / 
 
 // shared launch helpers (defined in plan.hip) --------------------------------
 fcs_status fcs_zero_fill(float *p, int64_t n, hipStream_t s);
+// Opt a kernel in to `bytes` of dynamic LDS above the 64 KB default, once per
+// kernel and device (so that launches captured into a graph make no
+// attribute calls after the first use).
+void fcs_allow_lds(const void *kernel, size_t bytes);
 int fcs_device_cu_count();
 
 // workspace sizes of each operation (defined next to the kernels)

@@ -2,6 +2,9 @@
 // device, status strings and small shared launch helpers.
 #include "fcs_internal.h"
 
+#include <map>
+#include <mutex>
+
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
@@ -35,6 +38,19 @@ extern "C" const char *fcs_status_str(fcs_status s) {
     case FCS_EUNSUPPORTED: return "FCS_EUNSUPPORTED: outside this build's limits";
     }
     return "unknown fcs_status";
+}
+
+void fcs_allow_lds(const void *kernel, size_t bytes) {
+    if (bytes <= 65536) return;
+    static std::mutex mu;
+    static std::map<std::pair<const void *, int>, size_t> done;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lock(mu);
+    size_t &have = done[{kernel, dev}];
+    if (have >= bytes) return;
+    if (hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) == hipSuccess)
+        have = bytes;
 }
 
 int fcs_device_cu_count() {
@@ -120,13 +136,16 @@ fcs_status fcs_zero_fill(float *p, int64_t n, hipStream_t s) {
 // transform length: L = Q * P, P a power of two in [FCS_MIN_FFT, FCS_MAX_FFT]
 // ---------------------------------------------------------------------------
 static double cp_cost(const fcs_plan *p, int64_t P, int Q) {
-    // per (sketch, rank): for each stored slice and mode, a scatter of I_n
-    // factor entries and one P-point FFT (cost model, arbitrary units)
+    // per (sketch, rank) and stored slice: for each mode a count-sketch
+    // gather over its J_n buckets and I_n entries (about four memory
+    // operations per bucket or entry) and one P-point FFT (about one unit per
+    // point and radix-2 stage); plus the inverse of the slice
     const int Qh = Q / 2 + 1;
-    double lg = std::log2((double)P);
+    const double lg = std::log2((double)P);
+    const double fft = (double)P * lg;
     double per_mode = 0.0;
-    for (int n = 0; n < p->N; ++n) per_mode += 3.0 * (double)p->I[n] + (double)P * lg;
-    return (double)Qh * per_mode;
+    for (int n = 0; n < p->N; ++n) per_mode += 4.0 * (double)(p->J[n] + p->I[n]) + fft;
+    return (double)Qh * (per_mode + fft);
 }
 
 static bool choose_transform(fcs_plan *p, int64_t Lreq) {

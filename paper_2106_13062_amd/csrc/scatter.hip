@@ -512,9 +512,7 @@ DenseLaunch plan_dense(const fcs_plan *p) {
 // (static LDS of the kernel comes on top, within the 160 KB of a CU).
 template <typename K>
 void allow_lds(K kernel, size_t bytes) {
-    if (bytes > 65536)
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    fcs_allow_lds(reinterpret_cast<const void *>(kernel), bytes);
 }
 
 template <int DG, int NV>

@@ -214,6 +214,15 @@ def batch_instances(count: int = 4096, seed: int = DATA_SEED["batch4096"],
     return out
 
 
+def instance_inputs(instances, workers: int = _WORKERS):
+    """Factors of every instance, drawn in parallel (numpy releases the GIL
+    while drawing); yields (instance, factors) in order."""
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=max(1, workers)) as ex:
+        for ins, f in zip(instances, ex.map(lambda i: i.factors(), instances)):
+            yield ins, f
+
+
 def poisson_arrivals(seed: int, rate: float, count: int) -> np.ndarray:
     """Arrival times (s) of a Poisson stream: cumulative exponential gaps."""
     return np.cumsum(rng(seed, 11).exponential(1.0 / rate, size=count))
