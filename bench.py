@@ -359,6 +359,108 @@ def batch_workload(args, torch, dev):
     return res
 
 
+def serve_setup(torch, dev, args):
+    """Server with the resident order-3 10^4 sketch (D = 10) and its bank of
+    (u, v) pairs, CP build inputs from the uneven-batch shape distribution
+    (D = 10) and COO tensors of order 3 (1024^3, J_n = 4096, D = 8) with nnz
+    log-uniform in [1e4, 1e8], all pre-staged on the device."""
+    import synth
+    from paper_2106_13062_amd.serve import Server
+    srv = Server(dev, streams=4, cap_bytes=200e9, max_group=256, max_inflight=8)
+    cfg = synth.CP10K
+    plan = srv.plan(cfg.I, cfg.J, cfg.D, cfg.hash_seed)
+    U = [torch.from_numpy(u).to(dev).t().contiguous() for u in cfg.factors()]
+    _, spec = plan.sketch_cp(U, want_out=False, want_spec=True)
+    del U
+    npairs = args.serve_pairs
+    uv = synth.unit_vectors(cfg.data_seed, 2 * npairs, cfg.I[1], stream=6)
+    srv.add_resident_sketch("cp10k", plan, spec, torch.from_numpy(uv[:npairs]).to(dev),
+                            torch.from_numpy(uv[npairs:]).to(dev))
+    insts = synth.batch_instances(args.serve_cp, seed=synth.DATA_SEED["batch4096"] + 17,
+                                  hash_seed=synth.HASH_SEED["batch4096"] + 17, kron_every=0)
+    for k, (ins, F) in enumerate(synth.instance_inputs(insts)):
+        p = srv.plan(ins.I, ins.J, 10, ins.hash_seed)
+        srv.add_input(f"cp{k}", "cp", p, [torch.from_numpy(u).to(dev).t().contiguous() for u in F])
+    d = synth.DENSE1024
+    pc = srv.plan(d.I, d.J, d.D, d.hash_seed)
+    g = torch.Generator(device=dev)
+    g.manual_seed(synth.DATA_SEED["dense1024"] + 5)
+    nnzs = synth.coo_nnz_sizes(synth.DATA_SEED["dense1024"] + 5, args.serve_coo)
+    for k, nnz in enumerate(nnzs):
+        idx = torch.stack([torch.randint(0, i, (nnz,), generator=g, device=dev, dtype=torch.int32) for i in d.I])
+        val = torch.randn(nnz, generator=g, device=dev)
+        srv.add_input(f"coo{k}", "coo", pc, idx.contiguous(), val)
+    torch.cuda.synchronize()
+    return srv, nnzs
+
+
+def serve_requests(srv, args, rate, count, seed):
+    import synth
+    reqs = []
+    for rid, (t, kind, i) in enumerate(synth.serving_requests(seed, rate, count, args.serve_pairs,
+                                                              args.serve_cp, args.serve_coo)):
+        key = {"contract": "cp10k", "cp": f"cp{i}", "coo": f"coo{i}"}[kind]
+        reqs.append(srv.make_request(rid, kind, t, key, index=i if kind == "contract" else 0))
+    return reqs
+
+
+def serve_workload(args, torch, dev):
+    """Poisson request streams at several rates through the continuous
+    batching server, against the same requests served one at a time."""
+    from paper_2106_13062_amd.serve import Request, latency_stats, run_alone
+    t0 = time.perf_counter()
+    srv, nnzs = serve_setup(torch, dev, args)
+    log(f"serve: set up in {time.perf_counter() - t0:.1f} s (COO nnz {nnzs})")
+    # warm every kind of launch (allocator, first-use attributes)
+    for r in serve_requests(srv, args, 1e3, 64, 999):
+        run_alone(srv, r)
+    srv.run(serve_requests(srv, args, 5e4, 256, 998), timeout=120)
+    torch.cuda.synchronize()
+    rates = [float(x) for x in args.serve_rates.split(",")]
+    out = {"workload": "serve: Poisson mix of 90% T(I,u,v) on the resident order-3 10^4 D=10 sketch, "
+                       "8% CP builds (uneven-batch shapes, D=10), 2% COO sketches (1024^3, D=8, nnz "
+                       "log-uniform 1e4-1e8); admission cap 200 GB, 4 streams",
+           "rates": []}
+    for k, rate in enumerate(rates):
+        n = int(min(args.serve_max, max(200, rate * args.serve_seconds)))
+        reqs = serve_requests(srv, args, rate, n, 100 + k)
+        wall = srv.run(reqs, timeout=300)
+        st = latency_stats(reqs)
+        sk = sum(r.sketches for r in reqs)
+        row = {"offered_req_s": rate, "requests": n, "wall_s": wall, "served_req_s": n / wall,
+               "sketches_per_s": sk / wall, **st}
+        out["rates"].append(row)
+        log(f"serve rate {rate:g}: {row}")
+        for r in reqs:
+            r.result = None
+    # one request at a time on the same stream, each waited for
+    reqs = serve_requests(srv, args, rates[-1], int(min(args.serve_max, 4000)), 100 + len(rates) - 1)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for r in reqs:
+        run_alone(srv, r)
+        r.result = None
+    plain_s = time.perf_counter() - t1
+    sk = sum(r.sketches for r in reqs)
+    out["plain"] = {"requests": len(reqs), "wall_s": plain_s, "req_s": len(reqs) / plain_s,
+                    "sketches_per_s": sk / plain_s}
+    best = max(out["rates"], key=lambda x: x["served_req_s"])
+    out["served_vs_plain_req_s"] = best["served_req_s"] / out["plain"]["req_s"]
+    # alone-versus-mix parity on a sample of a mixed run
+    reqs = serve_requests(srv, args, rates[len(rates) // 2], 600, 4242)
+    srv.run(reqs, timeout=120)
+    worst = 0.0
+    for r in reqs[::6]:
+        alone = Request(r.rid, r.kind, 0.0, r.key, r.index)
+        run_alone(srv, alone)
+        a = (r.result[0][r.result[1]] if r.kind == "contract" else r.result).double()
+        b = (alone.result[0][alone.result[1]] if r.kind == "contract" else alone.result).double()
+        nb = torch.linalg.vector_norm(b).item()
+        worst = max(worst, torch.linalg.vector_norm(a - b).item() / (nb if nb > 0 else 1.0))
+    out["max_rel_err_mix_vs_alone"] = worst
+    return out
+
+
 def copy_calibration(torch, dev, nbytes=1 << 30, reps=5):
     """A plain device-to-device copy of known size, for scaling the
     FETCH_SIZE / WRITE_SIZE counters of the profiled kernels."""
@@ -379,12 +481,19 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=1 << 19,
                     help="rows of the tensor the CPU oracle sketches")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "dense1024_traffic.json"))
-    ap.add_argument("--mode", default="full", choices=["full", "dense", "batch", "copy"],
+    ap.add_argument("--mode", default="full", choices=["full", "dense", "batch", "serve", "copy"],
                     help="full: headline + secondary workloads; dense: headline only; "
-                         "batch: the uneven batch only; copy: plain copy kernel for counter calibration")
+                         "batch: the uneven batch only; serve: the serving loop only; "
+                         "copy: plain copy kernel for counter calibration")
     ap.add_argument("--batch-count", type=int, default=4096, help="instances of the uneven batch")
     ap.add_argument("--batch-reps", type=int, default=3, help="timed passes of each batch path")
     ap.add_argument("--no-tune", dest="tune", action="store_false", help="skip the batch autotuner")
+    ap.add_argument("--serve-rates", default="2000,5000,10000,20000,50000", help="offered request rates (1/s)")
+    ap.add_argument("--serve-seconds", type=float, default=0.5, help="arrival span per rate")
+    ap.add_argument("--serve-max", type=int, default=25000, help="most requests per rate")
+    ap.add_argument("--serve-pairs", type=int, default=1024, help="(u, v) pairs in the bank")
+    ap.add_argument("--serve-cp", type=int, default=32, help="pre-staged CP build inputs")
+    ap.add_argument("--serve-coo", type=int, default=6, help="pre-staged COO tensors")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
@@ -403,6 +512,9 @@ def main():
     if args.mode == "batch":
         print(json.dumps({"batch": batch_workload(args, torch, dev)}), flush=True)
         return
+    if args.mode == "serve":
+        print(json.dumps({"serve": serve_workload(args, torch, dev)}), flush=True)
+        return
     cfg, res, cpu, T = dense_workload(args, torch, dev)
     secondary = {}
     if args.mode == "full":
@@ -417,6 +529,9 @@ def main():
         T = None
         log("secondary: uneven batch")
         secondary["batch"] = batch_workload(args, torch, dev)
+        torch.cuda.empty_cache()
+        log("secondary: serving loop")
+        secondary["serve"] = serve_workload(args, torch, dev)
     del T
     traffic = None
     if os.path.exists(args.traffic_json):

@@ -226,3 +226,26 @@ def instance_inputs(instances, workers: int = _WORKERS):
 def poisson_arrivals(seed: int, rate: float, count: int) -> np.ndarray:
     """Arrival times (s) of a Poisson stream: cumulative exponential gaps."""
     return np.cumsum(rng(seed, 11).exponential(1.0 / rate, size=count))
+
+
+SERVE_MIX = (0.90, 0.08, 0.02)      # contraction, CP build, COO sketch
+
+
+def serving_requests(seed: int, rate: float, count: int, n_pairs: int, n_cp: int, n_coo: int,
+                     mix=SERVE_MIX):
+    """(arrival s, kind, input index) of a Poisson request stream: kinds
+    drawn with probabilities `mix`, each referring to one of the pre-staged
+    inputs (vector pairs, CP factor sets, COO tensors) uniformly."""
+    t = poisson_arrivals(seed, rate, count)
+    g = rng(seed, 12)
+    kinds = g.choice(3, size=count, p=np.asarray(mix) / np.sum(mix))
+    idx = np.where(kinds == 0, g.integers(0, n_pairs, size=count),
+                   np.where(kinds == 1, g.integers(0, n_cp, size=count), g.integers(0, n_coo, size=count)))
+    names = ("contract", "cp", "coo")
+    return [(float(t[k]), names[int(kinds[k])], int(idx[k])) for k in range(count)]
+
+
+def coo_nnz_sizes(seed: int, count: int, lo: float = 1e4, hi: float = 1e8) -> list:
+    """nnz of the pre-staged COO tensors: log-uniform in [lo, hi]."""
+    g = rng(seed, 13)
+    return [int(np.exp(g.uniform(np.log(lo), np.log(hi)))) for _ in range(count)]
