@@ -198,7 +198,8 @@ def batch_items(torch, dev, insts, facs, gather_weight=None):
     items = []
     for ins, U in zip(insts, facs):
         if ins.kind == "kron":
-            plan = Plan(ins.I, ins.J, ins.D, ins.hash_seed, L=max(4 * ins.J[0], 256), device=dev)
+            # a 16384-point transform gives the factor scatters 1024 threads
+            plan = Plan(ins.I, ins.J, ins.D, ins.hash_seed, L=max(4 * ins.J[0], 16384), device=dev)
         else:
             L = 0 if gather_weight is None else choose_length(ins.I, ins.J, gather_weight)
             plan = Plan(ins.I, ins.J, ins.D, ins.hash_seed, L=L, device=dev)
@@ -481,10 +482,10 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=1 << 19,
                     help="rows of the tensor the CPU oracle sketches")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "dense1024_traffic.json"))
-    ap.add_argument("--mode", default="full", choices=["full", "dense", "batch", "serve", "copy"],
-                    help="full: headline + secondary workloads; dense: headline only; "
-                         "batch: the uneven batch only; serve: the serving loop only; "
-                         "copy: plain copy kernel for counter calibration")
+    ap.add_argument("--mode", default="full", choices=["full", "dense", "cp", "batch", "serve", "copy"],
+                    help="full: headline + secondary workloads; dense: headline only; cp: the CP "
+                         "sketches and T(I,u,v) only; batch: the uneven batch only; serve: the "
+                         "serving loop only; copy: plain copy kernel for counter calibration")
     ap.add_argument("--batch-count", type=int, default=4096, help="instances of the uneven batch")
     ap.add_argument("--batch-reps", type=int, default=3, help="timed passes of each batch path")
     ap.add_argument("--no-tune", dest="tune", action="store_false", help="skip the batch autotuner")
@@ -514,6 +515,12 @@ def main():
         return
     if args.mode == "serve":
         print(json.dumps({"serve": serve_workload(args, torch, dev)}), flush=True)
+        return
+    if args.mode == "cp":
+        import synth
+        print(json.dumps({"cp100": cp_workload(args, torch, dev, synth.CP100),
+                          "cp10k": cp_workload(args, torch, dev, synth.CP10K, pairs=synth.CP10K.pairs)}),
+              flush=True)
         return
     cfg, res, cpu, T = dense_workload(args, torch, dev)
     secondary = {}

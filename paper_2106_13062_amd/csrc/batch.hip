@@ -94,7 +94,7 @@ __device__ __forceinline__ void batch_tile(const BatchArgs &a, int t, float2 *ld
         __syncthreads();
         if (wg_atomic_ticket<P>(cnt, slot) != nch - 1) return;
         __threadfence();                 // acquire the other chunks' partials
-        slice_from_partials<P>(c, d, q, lds);
+        slice_from_partials<P>(c, d, q, lds, nch);
         atomicExch(cnt, 0);              // ready for the next run (every lane stores 0)
     }
     if (Qh == 1 || !c.out) return;
@@ -287,6 +287,9 @@ extern "C" fcs_status fcs_batch_create(const fcs_batch_item *items, int64_t coun
             if (it.R < 0) return fail((fcs_set_error("item %lld: R < 0", (long long)i), FCS_EINVAL));
             if (it.R > INT32_MAX) return fail((fcs_set_error("item %lld: R too large", (long long)i), FCS_EUNSUPPORTED));
             c.kind = FCS_DESC_CP;
+            for (int n = 0; n < p->N; ++n)
+                if (p->I[n] >= FCS_MAX_GATHER_INDEX)
+                    return fail((fcs_set_error("item %lld: CP sketches need I_n < 2^30", (long long)i), FCS_EUNSUPPORTED));
             c.R = (int)it.R;
             c.lambda = it.lambda;
             if (it.R == 0) {

@@ -50,11 +50,24 @@ __global__ __launch_bounds__(Shape<P>::T) void cp_forward_kernel(CpDesc c) {
         store_partial<P>(c, d, q, chunk, acc);
 }
 
-// One workgroup per (sketch, slice): sums the chunk partials and inverts.
+// Sum of the chunk partials of every (sketch, slice) into chunk slot 0, by
+// many workgroups (bandwidth bound): thread k of (d, q, block b) adds the
+// chunks of spectrum position b * 256 + k in chunk order.
+__global__ __launch_bounds__(256) void reduce_chunks_kernel(float2 *partial, int nchunks, int P, int blocks) {
+    const int dq = blockIdx.x / blocks;
+    const int k = (blockIdx.x % blocks) * 256 + threadIdx.x;
+    if (k >= P) return;
+    float2 *base = partial + (int64_t)dq * nchunks * P + k;
+    float2 acc = base[0];
+    for (int ch = 1; ch < nchunks; ++ch) acc = cadd(acc, base[(int64_t)ch * P]);
+    base[0] = acc;
+}
+
+// One workgroup per (sketch, slice): inverts the reduced spectrum.
 template <int P>
 __global__ __launch_bounds__(Shape<P>::T) void cp_finalize_kernel(CpDesc c) {
     extern __shared__ float2 lds[];
-    slice_from_partials<P>(c, blockIdx.x / c.s.Qh, blockIdx.x % c.s.Qh, lds);
+    slice_from_partials<P>(c, blockIdx.x / c.s.Qh, blockIdx.x % c.s.Qh, lds, 1);
 }
 
 // y_d = sum of the slice terms, in slice order.
@@ -144,7 +157,8 @@ __global__ __launch_bounds__(Shape<P>::T) void free_mode_kernel(FreeArgs a) {
         for (int n = 0; n < a.N; ++n) {
             if (n == f) continue;
             const int32_t *off = invd + a.ioff[n];
-            build_cs_slice<P>(lds, a.vecs[n] + (int64_t)p * a.I[n], off, off + a.J[n] + 1, a.J[n], q, a.s, 1.0f);
+            build_cs_slice<P>(lds, a.vecs[n] + (int64_t)p * a.I[n], off, off + a.J[n] + 1,
+                              off + a.J[n] + 1 + a.I[n], a.J[n], q, a.s, 1.0f);
             __syncthreads();
             float2 F[E];
             forward<P>(lds, a.s.twP, F);
@@ -210,8 +224,12 @@ void launch_cp(const CpDesc &c, hipStream_t s) {
     allow_lds_cp(cp_forward_kernel<P>, lds);
     allow_lds_cp(cp_finalize_kernel<P>, lds);
     hipLaunchKernelGGL(cp_forward_kernel<P>, dim3(c.D * c.s.Qh * c.nchunks), dim3(Shape<P>::T), lds, s, c);
-    if (c.nchunks > 1)
+    if (c.nchunks > 1) {
+        const int blocks = P / 256;
+        hipLaunchKernelGGL(reduce_chunks_kernel, dim3(c.D * c.s.Qh * blocks), dim3(256), 0, s, c.partial,
+                           c.nchunks, P, blocks);
         hipLaunchKernelGGL(cp_finalize_kernel<P>, dim3(c.D * c.s.Qh), dim3(Shape<P>::T), lds, s, c);
+    }
     if (c.s.Qh > 1 && c.out)
         hipLaunchKernelGGL(sum_slices_kernel, dim3((unsigned)fcs_ceil_div((int64_t)c.D * c.Jt, 256)), dim3(256), 0,
                            s, c);
@@ -284,6 +302,8 @@ extern "C" fcs_status fcs_sketch_cp(fcs_plan_t p, int64_t R, const float *const 
     if (R > INT32_MAX) FCS_FAIL(FCS_EUNSUPPORTED, "R too large");
     if (!out && !spec) FCS_FAIL(FCS_EINVAL, "neither out nor spec given");
     if (R > 0 && !U) FCS_FAIL(FCS_EINVAL, "null factor array");
+    for (int n = 0; n < p->N; ++n)
+        if (p->I[n] >= FCS_MAX_GATHER_INDEX) FCS_FAIL(FCS_EUNSUPPORTED, "CP sketches need I_n < 2^30");
     for (int n = 0; R > 0 && n < p->N; ++n)
         if (!U[n]) FCS_FAIL(FCS_EINVAL, "null factor %d", n);
     hipStream_t s = (hipStream_t)stream;
@@ -374,6 +394,8 @@ extern "C" fcs_status fcs_contract_free_mode(fcs_plan_t p, const float *spec, in
     if (free_mode < 0 || free_mode >= p->N) FCS_FAIL(FCS_EINVAL, "free_mode %d out of range", free_mode);
     if (Pn < 0) FCS_FAIL(FCS_EINVAL, "P < 0");
     if (Pn == 0) return FCS_OK;
+    for (int n = 0; n < p->N; ++n)
+        if (p->I[n] >= FCS_MAX_GATHER_INDEX) FCS_FAIL(FCS_EUNSUPPORTED, "contractions need I_n < 2^30");
     if (Pn > INT32_MAX / std::max<int>(1, p->D)) FCS_FAIL(FCS_EUNSUPPORTED, "too many vector tuples");
     if (!spec || !out || !vecs) FCS_FAIL(FCS_EINVAL, "null spectrum, output or vector array");
     for (int n = 0; n < p->N; ++n)

@@ -38,15 +38,35 @@ struct SliceArgs {
 };
 
 // Slice q of the DFT of one mode's count sketch CS_n(u): builds w_q in LDS
-// (natural order, padded).  u is the factor column (I_n floats), the inverse
-// lists give the buckets of h_n.  Each thread writes its own positions.  The
-// loads are issued in batches over the thread's E positions (bucket bounds,
-// then first entries, then factor values) so that their latencies overlap;
-// buckets with more than one entry (rare when J_n >= I_n) finish in a loop.
+// (natural order, padded).  u is the factor column (I_n floats); the inverse
+// lists give the buckets of h_n: `first` holds each bucket's first entry
+// (index, sign, more-entries flag), `off` / `ent` all entries in bucket
+// order.  Each thread writes its own positions.  A position costs two
+// dependent loads (first-entry word, factor value) unless its bucket holds
+// several entries; the loads of G positions are issued together so that
+// their latencies overlap.
+template <int P>
+__device__ __forceinline__ float bucket_rest(const float *__restrict__ u, const int32_t *__restrict__ off,
+                                             const int32_t *__restrict__ ent, int j) {
+    float y = 0.f;
+    const int c1 = off[j + 1];
+    for (int k = off[j] + 1; k < c1; ++k) {
+        const uint32_t w = (uint32_t)ent[k];
+        y += __uint_as_float(__float_as_uint(u[w & FCS_H_MASK]) ^ (w & FCS_S_BIT));
+    }
+    return y;
+}
+
+__device__ __forceinline__ float bucket_first(const float *__restrict__ u, uint32_t f) {
+    const float v = (f != FCS_FIRST_EMPTY) ? u[f & FCS_IDX_MASK] : 0.f;
+    return __uint_as_float(__float_as_uint(v) ^ (f & FCS_S_BIT));
+}
+
 template <int P>
 __device__ __forceinline__ void build_cs_slice(float2 *lds, const float *__restrict__ u,
                                                const int32_t *__restrict__ off,
-                                               const int32_t *__restrict__ ent, int Jn, int q,
+                                               const int32_t *__restrict__ ent,
+                                               const int32_t *__restrict__ first, int Jn, int q,
                                                const SliceArgs &s, float scale) {
     constexpr int T = Shape<P>::T;
     constexpr int E = Shape<P>::E;
@@ -54,32 +74,22 @@ __device__ __forceinline__ void build_cs_slice(float2 *lds, const float *__restr
     if (Jn <= P) {
         // positions t + e*T in groups of G (smaller groups for 1024-thread
         // workgroups, whose register budget is half)
-        constexpr int G = (T >= 1024) ? E / 4 : E;
+        constexpr int G = (T >= 1024) ? E / 2 : E;
 #pragma unroll
         for (int g0 = 0; g0 < E; g0 += G) {
-            int b0[G], b1[G];
+            uint32_t f[G];
 #pragma unroll
             for (int g = 0; g < G; ++g) {
                 const int j = t + (g0 + g) * T;
-                const bool in = j < Jn;
-                b0[g] = in ? off[j] : 0;
-                b1[g] = in ? off[j + 1] : 0;
+                f[g] = (j < Jn) ? (uint32_t)first[j] : FCS_FIRST_EMPTY;
             }
-            uint32_t e0[G];
-#pragma unroll
-            for (int g = 0; g < G; ++g) e0[g] = (b1[g] > b0[g]) ? (uint32_t)ent[b0[g]] : 0u;
             float y[G];
 #pragma unroll
-            for (int g = 0; g < G; ++g) {
-                const float v = (b1[g] > b0[g]) ? u[e0[g] & FCS_H_MASK] : 0.f;
-                y[g] = __uint_as_float(__float_as_uint(v) ^ (e0[g] & FCS_S_BIT));
-            }
+            for (int g = 0; g < G; ++g) y[g] = bucket_first(u, f[g]);
 #pragma unroll
             for (int g = 0; g < G; ++g) {
-                for (int k = b0[g] + 1; k < b1[g]; ++k) {
-                    const uint32_t w = (uint32_t)ent[k];
-                    y[g] += __uint_as_float(__float_as_uint(u[w & FCS_H_MASK]) ^ (w & FCS_S_BIT));
-                }
+                if (f[g] != FCS_FIRST_EMPTY && (f[g] & FCS_MORE_BIT))
+                    y[g] += bucket_rest<P>(u, off, ent, t + (g0 + g) * T);
             }
 #pragma unroll
             for (int g = 0; g < G; ++g) {
@@ -103,12 +113,9 @@ __device__ __forceinline__ void build_cs_slice(float2 *lds, const float *__restr
         float2 acc = make_float2(0.f, 0.f);
         int qt = 0;
         for (int j = m; j < Jn; j += P) {
-            float y = 0.f;
-            const int c0 = off[j], c1 = off[j + 1];
-            for (int k = c0; k < c1; ++k) {
-                const uint32_t w = (uint32_t)ent[k];
-                y += __uint_as_float(__float_as_uint(u[w & FCS_H_MASK]) ^ (w & FCS_S_BIT));
-            }
+            const uint32_t f = (uint32_t)first[j];
+            float y = bucket_first(u, f);
+            if (f != FCS_FIRST_EMPTY && (f & FCS_MORE_BIT)) y += bucket_rest<P>(u, off, ent, j);
             if (q == 0) {
                 acc.x += y;
             } else {
@@ -222,8 +229,8 @@ __device__ __forceinline__ void cp_tile(const CpDesc &c, int d, int q, int chunk
         const float lam = c.lambda ? c.lambda[r] : 1.0f;
         for (int n = 0; n < c.N; ++n) {
             const int32_t *off = invd + c.ioff[n];
-            build_cs_slice<P>(lds, c.U[n] + (int64_t)r * c.I[n], off, off + c.J[n] + 1, c.J[n], q, c.s,
-                              n == 0 ? lam : 1.0f);
+            build_cs_slice<P>(lds, c.U[n] + (int64_t)r * c.I[n], off, off + c.J[n] + 1,
+                              off + c.J[n] + 1 + c.I[n], c.J[n], q, c.s, n == 0 ? lam : 1.0f);
             __syncthreads();
             float2 v[E];
             forward<P>(lds, c.s.twP, v);
@@ -286,16 +293,18 @@ __device__ __forceinline__ float *slice_dst(const CpDesc &c, int d, int q) {
     return c.ytmp + ((int64_t)d * c.s.Qh + q) * c.Jt;
 }
 
-// Slice q of sketch d from its chunk partials (summed in a fixed order).
+// Slice q of sketch d from its chunk partials: the first `nsum` chunk
+// slots are summed in a fixed order (1 when an earlier pass already reduced
+// the chunks into slot 0).
 template <int P>
-__device__ __forceinline__ void slice_from_partials(const CpDesc &c, int d, int q, float2 *lds) {
+__device__ __forceinline__ void slice_from_partials(const CpDesc &c, int d, int q, float2 *lds, int nsum) {
     constexpr int E = Shape<P>::E;
     constexpr int T = Shape<P>::T;
     float2 X[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) X[e] = make_float2(0.f, 0.f);
     const float2 *src = c.partial + ((int64_t)d * c.s.Qh + q) * c.nchunks * P + tid_opaque();
-    for (int ch = 0; ch < c.nchunks; ++ch) {
+    for (int ch = 0; ch < nsum; ++ch) {
 #pragma unroll
         for (int e = 0; e < E; ++e) X[e] = cadd(X[e], src[(int64_t)ch * P + e * T]);
     }

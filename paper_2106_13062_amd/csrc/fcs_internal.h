@@ -16,6 +16,14 @@
 constexpr uint32_t FCS_H_MASK = 0x7fffffffu;
 constexpr uint32_t FCS_S_BIT = 0x80000000u;
 
+// First-entry word of a hash bucket (inverse lists): bits 0..29 the index of
+// the bucket's first entry, bit 30 set when the bucket holds more entries,
+// bit 31 that entry's sign.  FCS_FIRST_EMPTY marks an empty bucket.
+constexpr uint32_t FCS_IDX_MASK = 0x3fffffffu;
+constexpr uint32_t FCS_MORE_BIT = 0x40000000u;
+constexpr uint32_t FCS_FIRST_EMPTY = 0x7fffffffu;
+constexpr int64_t FCS_MAX_GATHER_INDEX = (int64_t)1 << 30;
+
 constexpr int FCS_MIN_FFT = 256;
 constexpr size_t FCS_LDS_BYTES = 160 * 1024;   // LDS per CU on gfx950
 
@@ -35,7 +43,8 @@ struct fcs_plan {
     const float2 *twL = nullptr;       // exp(-2 pi i k / L), k < L
     // inverse hash lists (buckets of h_n), per sketch a block of iblock words:
     // for mode n at ioff[n]: J_n + 1 bucket offsets, then I_n entries
-    // (index i | sign bit), entries of bucket j at [off[j], off[j+1])
+    // (index i | sign bit), entries of bucket j at [off[j], off[j+1]), then
+    // J_n first-entry words (FCS_IDX_MASK / FCS_MORE_BIT / FCS_FIRST_EMPTY)
     const int32_t *inv = nullptr;
     int64_t ioff[FCS_MAX_ORDER] = {0};
     int64_t iblock = 0;

@@ -145,6 +145,17 @@ __device__ __forceinline__ void pass(float2 *lds, const float2 *__restrict__ tw,
     constexpr int T = Shape<P>::T;
     constexpr int B = P / R / T;        // butterflies per thread
     const int t = tid_opaque();
+    // the pass's twiddles do not depend on the data: load them first so that
+    // their latency overlaps the LDS reads and the barrier
+    float2 w[NS > 1 ? B : 1][R];
+    if constexpr (NS > 1) {
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int jm = (t + T * b) % NS;
+#pragma unroll
+            for (int r = 1; r < R; ++r) w[b][r] = tw[r * jm * (P / (NS * R))];
+        }
+    }
 #pragma unroll
     for (int b = 0; b < B; ++b) {
         const int j = t + T * b;
@@ -159,9 +170,8 @@ __device__ __forceinline__ void pass(float2 *lds, const float2 *__restrict__ tw,
 #pragma unroll
         for (int r = 0; r < R; ++r) u[r] = v[b * R + r];
         if constexpr (NS > 1) {
-            const int jm = j % NS;
 #pragma unroll
-            for (int r = 1; r < R; ++r) u[r] = cmul(u[r], tw[r * jm * (P / (NS * R))]);
+            for (int r = 1; r < R; ++r) u[r] = cmul(u[r], w[b][r]);
         }
         dft<R>(u);
         if constexpr (LAST) {

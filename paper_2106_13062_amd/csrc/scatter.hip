@@ -81,6 +81,14 @@ struct DenseArgs {
     int nrow_modes;          // modes 1..nrow_modes vary along a block's rows
 };
 
+// 24-bit signed multiply (|a| < 2^22, b = +-1 here): one VALU op, with no
+// sign extension of the operands
+__device__ __forceinline__ int mul_i24(int a, int b) {
+    int r;
+    asm("v_mul_i32_i24 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
 // round to nearest (ties up) and convert: one VALU op
 __device__ __forceinline__ int cvt_rpi(float x) {
     int r;
@@ -148,7 +156,8 @@ __device__ __forceinline__ void scatter_slow(const DenseArgs &a, uint32_t qaddr,
 // Each value is scaled and rounded once (v_cvt_rpi); the column sign of
 // every sketch is a 24-bit integer multiply by +-1 and the row sign, uniform
 // across the wave, selects ds_sub_u32 instead of ds_add_u32.  A wave with an
-// out-of-range element in the row takes the float path for those elements.
+// out-of-range element in the row takes the float path for those elements
+// and adds zero for them to the bins.
 template <int DG, bool CHECK>
 __device__ __forceinline__ void scatter_seg(const DenseArgs &a, uint32_t qaddr, const float (&x)[4], float scale,
                                             int d0, const uint32_t (&A)[DG][4], const int (&S)[DG][4],
@@ -160,22 +169,24 @@ __device__ __forceinline__ void scatter_seg(const DenseArgs &a, uint32_t qaddr, 
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
         const float xs = x[e] * scale;
-        const bool ok = fabsf(xs) < QLIM;         // false for NaN / Inf too
-        slow |= (!ok) && (!CHECK || valid[e]);
-        q[e] = cvt_rpi(ok ? xs : 0.f);
+        slow |= !(fabsf(xs) < QLIM) && (!CHECK || valid[e]);   // NaN / Inf too
+        q[e] = cvt_rpi(xs);            // saturating; zeroed below when out of range
     }
-    if (__builtin_expect(__builtin_amdgcn_ballot_w64(slow) != 0, 0))
+    if (__builtin_expect(__builtin_amdgcn_ballot_w64(slow) != 0, 0)) {
         scatter_slow<DG, CHECK>(a, qaddr, x, scale, d0, A, S, valid, C, R, base, wsign);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) q[e] = (fabsf(x[e] * scale) < QLIM) ? q[e] : 0;
+    }
 #pragma unroll
     for (int d = 0; d < DG; ++d) {
         if (R[d]) {
 #pragma unroll
             for (int e = 0; e < 4; ++e)
-                if (!CHECK || valid[e]) lds_sub(A[d][e] + C[d], (uint32_t)__mul24(q[e], S[d][e]));
+                if (!CHECK || valid[e]) lds_sub(A[d][e] + C[d], (uint32_t)mul_i24(q[e], S[d][e]));
         } else {
 #pragma unroll
             for (int e = 0; e < 4; ++e)
-                if (!CHECK || valid[e]) lds_add(A[d][e] + C[d], (uint32_t)__mul24(q[e], S[d][e]));
+                if (!CHECK || valid[e]) lds_add(A[d][e] + C[d], (uint32_t)mul_i24(q[e], S[d][e]));
         }
     }
 }
