@@ -540,11 +540,18 @@ def main():
         log("secondary: serving loop")
         secondary["serve"] = serve_workload(args, torch, dev)
     del T
+    # HBM traffic per launch from the committed FETCH_SIZE / WRITE_SIZE
+    # summary, only while the kernel source is the one that was measured
     traffic = None
     if os.path.exists(args.traffic_json):
+        import hashlib
         with open(args.traffic_json) as f:
             t = json.load(f)
-        traffic = t.get("bytes_per_launch")
+        src = os.path.join(ROOT, t.get("source", ""))
+        if os.path.isfile(src):
+            with open(src, "rb") as f:
+                if hashlib.sha1(f.read()).hexdigest()[:12] == t.get("source_sha1"):
+                    traffic = t.get("bytes_per_launch")
     line = {
         "metric": METRIC,
         "value": res["value"],
