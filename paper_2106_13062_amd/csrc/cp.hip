@@ -106,10 +106,9 @@ __global__ __launch_bounds__(Shape<P>::T) void spectrum_kernel(SpecArgs a) {
     constexpr int T = Shape<P>::T;
     const int q = blockIdx.x % a.s.Qh;
     const int d = blockIdx.x / a.s.Qh;
-    build_seq_slice<P>(lds, a.y + (int64_t)d * a.Jt, (int)a.Jt, q, a.s);
-    __syncthreads();
     float2 v[E];
-    forward<P>(lds, a.s.twP, v);
+    build_seq_slice<P>(v, a.y + (int64_t)d * a.Jt, (int)a.Jt, q, a.s);
+    forward_regs<P>(lds, a.s.twP, v);
     float2 *sp = a.spec + ((int64_t)d * a.s.Qh + q) * P;
 #pragma unroll
     for (int e = 0; e < E; ++e) sp[threadIdx.x + e * T] = v[e];
@@ -157,11 +156,10 @@ __global__ __launch_bounds__(Shape<P>::T) void free_mode_kernel(FreeArgs a) {
         for (int n = 0; n < a.N; ++n) {
             if (n == f) continue;
             const int32_t *off = invd + a.ioff[n];
-            build_cs_slice<P>(lds, a.vecs[n] + (int64_t)p * a.I[n], off, off + a.J[n] + 1,
-                              off + a.J[n] + 1 + a.I[n], a.J[n], q, a.s, 1.0f);
-            __syncthreads();
             float2 F[E];
-            forward<P>(lds, a.s.twP, F);
+            build_cs_slice<P>(F, a.vecs[n] + (int64_t)p * a.I[n], off, off + a.J[n] + 1,
+                              off + a.J[n] + 1 + a.I[n], a.J[n], q, a.s, 1.0f);
+            forward_regs<P>(lds, a.s.twP, F);
 #pragma unroll
             for (int e = 0; e < E; ++e) X[e] = cmulc(X[e], F[e]);
         }
@@ -205,12 +203,48 @@ __global__ __launch_bounds__(256) void median_rows_kernel(const float *est, int6
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
+template <int P>
+int forward_occupancy() {
+    // resident forward workgroups per CU (LDS, registers, threads), asked of
+    // the runtime once per device
+    static int cached[64] = {0};
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    int &k = cached[dev & 63];
+    if (k == 0) {
+        fcs_allow_lds(reinterpret_cast<const void *>(cp_forward_kernel<P>), Lds<P>::bytes);
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void *>(cp_forward_kernel<P>),
+                                                         Shape<P>::T, Lds<P>::bytes) != hipSuccess || n < 1)
+            n = 1;
+        k = n;
+    }
+    return k;
+}
+
+// Rank chunks per (sketch, slice): the forward grid runs in rounds of
+// (resident workgroups per CU x CUs); the busiest CU handles
+// rounds x ceil(R / chunks) ranks.  Pick the count that minimises that
+// load (each extra chunk also costs one partial spectrum), fewest chunks on
+// ties.
 int cp_chunks(const fcs_plan *p, int64_t R) {
     if (R <= 0) return 1;
+    int occ = 1;
+    FCS_DISPATCH_FFT_NOFAIL(p->P, occ = forward_occupancy<PP>());
+    const int64_t slots = (int64_t)occ * fcs_device_cu_count();
     const int64_t tiles = (int64_t)p->D * p->Qh;
-    const int64_t waves = p->P >= 8192 ? 2 : 8;      // workgroups per CU that fit
-    const int64_t want = std::max<int64_t>(1, fcs_ceil_div(waves * fcs_device_cu_count(), tiles));
-    return (int)std::min<int64_t>(R, want);
+    int best = 1;
+    double best_cost = 0.0;
+    const int64_t hi = std::min<int64_t>(R, std::max<int64_t>(1, 4 * slots / std::max<int64_t>(1, tiles) + 1));
+    for (int64_t nch = 1; nch <= hi; ++nch) {
+        const int64_t rounds = fcs_ceil_div(tiles * nch, slots);
+        const double cost = (double)rounds * (double)fcs_ceil_div(R, nch) + 0.02 * (double)nch;
+        if (nch == 1 || cost < best_cost) {
+            best_cost = cost;
+            best = (int)nch;
+        }
+    }
+    return best;
 }
 
 template <typename K>

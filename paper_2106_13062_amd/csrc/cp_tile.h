@@ -27,6 +27,19 @@
     default: FCS_FAIL(FCS_EUNSUPPORTED, "FFT size %lld not built", (long long)(P_)); \
     }
 
+// The same dispatch for helpers that cannot fail (unknown sizes do nothing).
+#define FCS_DISPATCH_FFT_NOFAIL(P_, CALL)                    \
+    switch (P_) {                                            \
+    case 256: { constexpr int PP = 256; CALL; } break;       \
+    case 512: { constexpr int PP = 512; CALL; } break;       \
+    case 1024: { constexpr int PP = 1024; CALL; } break;     \
+    case 2048: { constexpr int PP = 2048; CALL; } break;     \
+    case 4096: { constexpr int PP = 4096; CALL; } break;     \
+    case 8192: { constexpr int PP = 8192; CALL; } break;     \
+    case 16384: { constexpr int PP = 16384; CALL; } break;   \
+    default: break;                                          \
+    }
+
 namespace fcscp {
 
 using namespace fcsfft;
@@ -37,14 +50,14 @@ struct SliceArgs {
     int L, P, Q, Qh;
 };
 
-// Slice q of the DFT of one mode's count sketch CS_n(u): builds w_q in LDS
-// (natural order, padded).  u is the factor column (I_n floats); the inverse
+// Slice q of the DFT of one mode's count sketch CS_n(u): the thread's
+// positions m = t + e*T of w_q, returned in registers w[e] (the inputs of
+// its first FFT pass).  u is the factor column (I_n floats); the inverse
 // lists give the buckets of h_n: `first` holds each bucket's first entry
 // (index, sign, more-entries flag), `off` / `ent` all entries in bucket
-// order.  Each thread writes its own positions.  A position costs two
-// dependent loads (first-entry word, factor value) unless its bucket holds
-// several entries; the loads of G positions are issued together so that
-// their latencies overlap.
+// order.  A position costs two dependent loads (first-entry word, factor
+// value) unless its bucket holds several entries; the loads of G positions
+// are issued together so that their latencies overlap.
 template <int P>
 __device__ __forceinline__ float bucket_rest(const float *__restrict__ u, const int32_t *__restrict__ off,
                                              const int32_t *__restrict__ ent, int j) {
@@ -63,7 +76,7 @@ __device__ __forceinline__ float bucket_first(const float *__restrict__ u, uint3
 }
 
 template <int P>
-__device__ __forceinline__ void build_cs_slice(float2 *lds, const float *__restrict__ u,
+__device__ __forceinline__ void build_cs_slice(float2 (&wv)[Shape<P>::E], const float *__restrict__ u,
                                                const int32_t *__restrict__ off,
                                                const int32_t *__restrict__ ent,
                                                const int32_t *__restrict__ first, int Jn, int q,
@@ -96,10 +109,10 @@ __device__ __forceinline__ void build_cs_slice(float2 *lds, const float *__restr
                 const int m = t + (g0 + g) * T;
                 const float ys = y[g] * scale;
                 if (q == 0) {
-                    lds[pad(m)] = make_float2(ys, 0.f);
+                    wv[g0 + g] = make_float2(ys, 0.f);
                 } else {
                     const float2 w = s.twL[q * m];     // q m < Q P = L
-                    lds[pad(m)] = make_float2(ys * w.x, ys * w.y);
+                    wv[g0 + g] = make_float2(ys * w.x, ys * w.y);
                 }
             }
         }
@@ -109,7 +122,9 @@ __device__ __forceinline__ void build_cs_slice(float2 *lds, const float *__restr
     // exp(-2 pi i q (m + tP) / L) = exp(-2 pi i q m / L) exp(-2 pi i q t / Q):
     // the fold sums with the Q-th roots (index q t mod Q, kept incrementally)
     // and applies the position twist once.
-    for (int m = t; m < P; m += T) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int m = t + e * T;
         float2 acc = make_float2(0.f, 0.f);
         int qt = 0;
         for (int j = m; j < Jn; j += P) {
@@ -127,17 +142,21 @@ __device__ __forceinline__ void build_cs_slice(float2 *lds, const float *__restr
             }
         }
         if (q != 0) acc = cmul(acc, s.twL[q * m]);
-        lds[pad(m)] = make_float2(acc.x * scale, acc.y * scale);
+        wv[e] = make_float2(acc.x * scale, acc.y * scale);
     }
 }
 
-// Slice q of the DFT of a dense real sequence y[0..M): w_q in LDS (same
-// factorised twist as the fold above).
+// Slice q of the DFT of a dense real sequence y[0..M): the thread's
+// positions of w_q in registers (same factorised twist as the fold above).
 template <int P>
-__device__ __forceinline__ void build_seq_slice(float2 *lds, const float *__restrict__ y, int M, int q,
-                                                const SliceArgs &s) {
+__device__ __forceinline__ void build_seq_slice(float2 (&wv)[Shape<P>::E], const float *__restrict__ y, int M,
+                                                int q, const SliceArgs &s) {
     constexpr int T = Shape<P>::T;
-    for (int m = tid_opaque(); m < P; m += T) {
+    constexpr int E = Shape<P>::E;
+    const int t = tid_opaque();
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int m = t + e * T;
         float2 acc = make_float2(0.f, 0.f);
         int qt = 0;
         for (int j = m; j < M; j += P) {
@@ -153,7 +172,7 @@ __device__ __forceinline__ void build_seq_slice(float2 *lds, const float *__rest
             }
         }
         if (q != 0) acc = cmul(acc, s.twL[q * m]);
-        lds[pad(m)] = acc;
+        wv[e] = acc;
     }
 }
 
@@ -229,11 +248,10 @@ __device__ __forceinline__ void cp_tile(const CpDesc &c, int d, int q, int chunk
         const float lam = c.lambda ? c.lambda[r] : 1.0f;
         for (int n = 0; n < c.N; ++n) {
             const int32_t *off = invd + c.ioff[n];
-            build_cs_slice<P>(lds, c.U[n] + (int64_t)r * c.I[n], off, off + c.J[n] + 1,
-                              off + c.J[n] + 1 + c.I[n], c.J[n], q, c.s, n == 0 ? lam : 1.0f);
-            __syncthreads();
             float2 v[E];
-            forward<P>(lds, c.s.twP, v);
+            build_cs_slice<P>(v, c.U[n] + (int64_t)r * c.I[n], off, off + c.J[n] + 1,
+                              off + c.J[n] + 1 + c.I[n], c.J[n], q, c.s, n == 0 ? lam : 1.0f);
+            forward_regs<P>(lds, c.s.twP, v);
 #pragma unroll
             for (int e = 0; e < E; ++e) prod[e] = (n == 0) ? v[e] : cmul(prod[e], v[e]);
         }
@@ -412,14 +430,12 @@ __device__ __forceinline__ void kron_sketch(const CpDesc &c, int d, float2 *lds)
     __threadfence_block();
     __syncthreads();
     for (int q = 0; q < c.s.Qh; ++q) {
-        build_seq_slice<P>(lds, ya, na, q, c.s);
-        __syncthreads();
         float2 X[E];
-        forward<P>(lds, c.s.twP, X);
-        build_seq_slice<P>(lds, yb, nbb, q, c.s);
-        __syncthreads();
+        build_seq_slice<P>(X, ya, na, q, c.s);
+        forward_regs<P>(lds, c.s.twP, X);
         float2 Y[E];
-        forward<P>(lds, c.s.twP, Y);
+        build_seq_slice<P>(Y, yb, nbb, q, c.s);
+        forward_regs<P>(lds, c.s.twP, Y);
 #pragma unroll
         for (int e = 0; e < E; ++e) X[e] = cmul(X[e], Y[e]);
         finish_slice<P>(c, d, q, lds, X, c.out ? c.out + (int64_t)d * c.Jt : nullptr, q > 0);

@@ -156,11 +156,20 @@ __device__ __forceinline__ void pass(float2 *lds, const float2 *__restrict__ tw,
             for (int r = 1; r < R; ++r) w[b][r] = tw[r * jm * (P / (NS * R))];
         }
     }
+    // pad(i + c) = pad(i) + c + c / 16 when c is a multiple of 16: one
+    // padded base per butterfly and constant offsets
+    constexpr int SR = P / R;
 #pragma unroll
     for (int b = 0; b < B; ++b) {
         const int j = t + T * b;
+        if constexpr (SR % 16 == 0) {
+            const float2 *src = lds + pad(j);
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[b * R + r] = lds[pad(j + r * (P / R))];
+            for (int r = 0; r < R; ++r) v[b * R + r] = src[r * (SR + SR / 16)];
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[b * R + r] = lds[pad(j + r * SR)];
+        }
     }
     __syncthreads();
 #pragma unroll
@@ -180,8 +189,14 @@ __device__ __forceinline__ void pass(float2 *lds, const float2 *__restrict__ tw,
             for (int r = 0; r < R; ++r) v[r] = u[r];
         } else {
             const int idxD = (j / NS) * NS * R + (j % NS);
+            if constexpr (NS % 16 == 0) {
+                float2 *dst = lds + pad(idxD);
 #pragma unroll
-            for (int r = 0; r < R; ++r) lds[pad(idxD + r * NS)] = u[r];
+                for (int r = 0; r < R; ++r) dst[r * (NS + NS / 16)] = u[r];
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; ++r) lds[pad(idxD + r * NS)] = u[r];
+            }
         }
     }
     if constexpr (!LAST) __syncthreads();
@@ -213,6 +228,46 @@ __device__ __forceinline__ void forward(float2 *lds, const float2 *__restrict__ 
     }
 }
 
+// Forward FFT of values the thread already holds: v[e] = x[t + e*T] (its own
+// natural-order positions, which are exactly the inputs of its first-pass
+// butterflies).  The first pass reads no LDS and needs no barrier before it;
+// returns X[t + e*T] in v.  lds is clobbered and must not be in use.
+template <int P>
+__device__ __forceinline__ void forward_regs(float2 *lds, const float2 *__restrict__ tw, float2 (&v)[Shape<P>::E]) {
+    using S = Shape<P>;
+    constexpr int T = S::T;
+    constexpr int E = S::E;
+    constexpr int R0 = S::R0;
+    constexpr int B = E / R0;
+    static_assert(S::NPASS >= 2, "first pass is never the last");
+    const int t = tid_opaque();
+    // first pass (NS = 1): butterfly b takes x[j + r P/R0], j = t + T b,
+    // that is v[b + r B]; its outputs go to positions j R0 + r
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        float2 u[R0];
+#pragma unroll
+        for (int r = 0; r < R0; ++r) u[r] = v[b + r * B];
+        dft<R0>(u);
+        const int j = t + T * b;
+#pragma unroll
+        for (int r = 0; r < R0; ++r) lds[pad(j * R0 + r)] = u[r];
+    }
+    __syncthreads();
+    if constexpr (S::NPASS == 2) {
+        pass<P, E, R0, true>(lds, tw, v);
+    } else {
+        pass<P, E, R0, false>(lds, tw, v);
+        if constexpr (S::NPASS == 3) {
+            pass<P, E, R0 * E, true>(lds, tw, v);
+        } else {
+            pass<P, E, R0 * E, false>(lds, tw, v);
+            static_assert(S::NPASS == 4, "P <= 16384");
+            pass<P, E, R0 * E * E, true>(lds, tw, v);
+        }
+    }
+}
+
 // Unnormalised inverse transform (exp(+2 pi i jk/P)) of the values in lds,
 // through conj(FFT(conj(x))).  Returns x[t + e*T] in out[e].
 template <int P>
@@ -232,9 +287,10 @@ __device__ __forceinline__ void inverse(float2 *lds, const float2 *__restrict__ 
 template <int P>
 __device__ __forceinline__ void store(float2 *lds, const float2 (&v)[Shape<P>::E]) {
     constexpr int T = Shape<P>::T;
-    const int t = tid_opaque();
+    static_assert(T % 16 == 0, "thread count is a multiple of 16");
+    float2 *dst = lds + pad(tid_opaque());
 #pragma unroll
-    for (int e = 0; e < Shape<P>::E; ++e) lds[pad(t + e * T)] = v[e];
+    for (int e = 0; e < Shape<P>::E; ++e) dst[e * (T + T / 16)] = v[e];
 }
 
 }  // namespace fcsfft
