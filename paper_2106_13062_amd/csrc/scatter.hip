@@ -620,28 +620,58 @@ __global__ __launch_bounds__(COO_THREADS) void coo_scatter_kernel(CooArgs a) {
     const float scale = ldexpf(1.0f, F);
     const float inv = ldexpf(1.0f, -F);
 
-    for (int64_t k = k0 + threadIdx.x; k < k1; k += COO_THREADS) {
-        const float x = a.val[k];
-        const float xs = x * scale;
-        const bool ok = fabsf(xs) < QLIM32;
-        int ix[FCS_MAX_ORDER];
-        for (int n = 0; n < a.N; ++n) ix[n] = a.idx[(int64_t)n * a.nnz + k] + (int)a.off[n];
+    // U entries per thread per step: their coordinate and value loads are
+    // all issued before any is used, so one workgroup per CU keeps enough
+    // loads in flight
+    constexpr int U = 8;
+    for (int64_t kb = k0 + threadIdx.x; kb < k1; kb += (int64_t)COO_THREADS * U) {
+        float x[U];
+        int H[U][DG];
+        uint32_t S[U][DG];
 #pragma unroll
-        for (int d = 0; d < DG; ++d) {
-            if (d < nd) {
-                int H = 0;
-                uint32_t S = 0;
-                for (int n = 0; n < a.N; ++n) {
-                    const uint32_t p = tabs[d * sumI + ix[n]];
-                    H += (int)(p & FCS_H_MASK);
-                    S ^= p & FCS_S_BIT;
+        for (int u = 0; u < U; ++u) {
+            const int64_t k = kb + (int64_t)u * COO_THREADS;
+            x[u] = k < k1 ? a.val[k] : 0.f;
+#pragma unroll
+            for (int d = 0; d < DG; ++d) {
+                H[u][d] = 0;
+                S[u][d] = 0;
+            }
+        }
+        for (int n = 0; n < a.N; ++n) {
+            const int32_t *col = a.idx + (int64_t)n * a.nnz;
+            int ix[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t k = kb + (int64_t)u * COO_THREADS;
+                ix[u] = (k < k1 ? col[k] : 0) + (int)a.off[n];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+#pragma unroll
+                for (int d = 0; d < DG; ++d) {
+                    const uint32_t p = tabs[d * sumI + ix[u]];
+                    H[u][d] += (int)(p & FCS_H_MASK);
+                    S[u][d] ^= p & FCS_S_BIT;
                 }
-                if (ok) {
-                    const int q = cvt_rpi(__uint_as_float(__float_as_uint(xs) ^ S));
-                    __hip_atomic_fetch_add(&bins[d * Jt + H], (unsigned long long)(long long)q,
-                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                } else {
-                    unsafeAtomicAdd(a.out + (int64_t)(d0 + d) * a.Jt + H, __uint_as_float(__float_as_uint(x) ^ S));
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (kb + (int64_t)u * COO_THREADS >= k1) continue;
+            const float xs = x[u] * scale;
+            const bool ok = fabsf(xs) < QLIM32;
+#pragma unroll
+            for (int d = 0; d < DG; ++d) {
+                if (d < nd) {
+                    if (ok) {
+                        const int q = cvt_rpi(__uint_as_float(__float_as_uint(xs) ^ S[u][d]));
+                        __hip_atomic_fetch_add(&bins[d * Jt + H[u][d]], (unsigned long long)(long long)q,
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    } else {
+                        unsafeAtomicAdd(a.out + (int64_t)(d0 + d) * a.Jt + H[u][d],
+                                        __uint_as_float(__float_as_uint(x[u]) ^ S[u][d]));
+                    }
                 }
             }
         }
