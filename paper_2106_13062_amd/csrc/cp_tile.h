@@ -85,6 +85,10 @@ __device__ __forceinline__ void build_cs_slice(float2 (&wv)[Shape<P>::E], const 
     constexpr int E = Shape<P>::E;
     const int t = tid_opaque();
     if (Jn <= P) {
+        // slice twist exp(-2 pi i q (t + eT) / L) = exp(-2 pi i q t / L) *
+        // exp(-2 pi i q e T / L): one per-thread factor and E factors that
+        // are the same for every thread (q e T < Q P = L)
+        const float2 wt = (q == 0) ? make_float2(1.f, 0.f) : s.twL[q * t];
         // positions t + e*T in groups of G (smaller groups for 1024-thread
         // workgroups, whose register budget is half)
         constexpr int G = (T >= 1024) ? E / 2 : E;
@@ -106,12 +110,11 @@ __device__ __forceinline__ void build_cs_slice(float2 (&wv)[Shape<P>::E], const 
             }
 #pragma unroll
             for (int g = 0; g < G; ++g) {
-                const int m = t + (g0 + g) * T;
                 const float ys = y[g] * scale;
                 if (q == 0) {
                     wv[g0 + g] = make_float2(ys, 0.f);
                 } else {
-                    const float2 w = s.twL[q * m];     // q m < Q P = L
+                    const float2 w = cmul(wt, s.twL[q * (g0 + g) * T]);
                     wv[g0 + g] = make_float2(ys * w.x, ys * w.y);
                 }
             }

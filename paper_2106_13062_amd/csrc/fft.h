@@ -145,15 +145,23 @@ __device__ __forceinline__ void pass(float2 *lds, const float2 *__restrict__ tw,
     constexpr int T = Shape<P>::T;
     constexpr int B = P / R / T;        // butterflies per thread
     const int t = tid_opaque();
-    // the pass's twiddles do not depend on the data: load them first so that
-    // their latency overlaps the LDS reads and the barrier
+    // the pass's twiddles do not depend on the data: their loads are issued
+    // first so that the latency overlaps the LDS reads and the barrier.  For
+    // radix 8 and 16 only W^1 and W^4 are loaded and the other powers are
+    // formed by at most three complex products (error a few ulp).
     float2 w[NS > 1 ? B : 1][R];
     if constexpr (NS > 1) {
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             const int jm = (t + T * b) % NS;
+            constexpr int st = P / (NS * R);
+            if constexpr (R >= 8) {
+                w[b][1] = tw[jm * st];
+                w[b][4] = tw[4 * jm * st];
+            } else {
 #pragma unroll
-            for (int r = 1; r < R; ++r) w[b][r] = tw[r * jm * (P / (NS * R))];
+                for (int r = 1; r < R; ++r) w[b][r] = tw[r * jm * st];
+            }
         }
     }
     // pad(i + c) = pad(i) + c + c / 16 when c is a multiple of 16: one
@@ -179,6 +187,19 @@ __device__ __forceinline__ void pass(float2 *lds, const float2 *__restrict__ tw,
 #pragma unroll
         for (int r = 0; r < R; ++r) u[r] = v[b * R + r];
         if constexpr (NS > 1) {
+            if constexpr (R >= 8) {
+                float2 (&x)[R] = w[b];
+                x[2] = cmul(x[1], x[1]);
+                x[3] = cmul(x[2], x[1]);
+                x[5] = cmul(x[4], x[1]);
+                x[6] = cmul(x[4], x[2]);
+                x[7] = cmul(x[4], x[3]);
+                if constexpr (R == 16) {
+                    x[8] = cmul(x[4], x[4]);
+#pragma unroll
+                    for (int r = 9; r < 16; ++r) x[r] = cmul(x[8], x[r - 8]);
+                }
+            }
 #pragma unroll
             for (int r = 1; r < R; ++r) u[r] = cmul(u[r], w[b][r]);
         }
