@@ -193,16 +193,10 @@ def batch_inputs(torch, dev, count):
 def batch_items(torch, dev, insts, facs, gather_weight=None):
     """Plans and outputs of every instance; CP transform lengths from the
     length model with the given gather weight (None: the planner's)."""
-    from paper_2106_13062_amd import Plan
-    from paper_2106_13062_amd.autotune import choose_length
+    from paper_2106_13062_amd.autotune import plan_for
     items = []
     for ins, U in zip(insts, facs):
-        if ins.kind == "kron":
-            # a 16384-point transform gives the factor scatters 1024 threads
-            plan = Plan(ins.I, ins.J, ins.D, ins.hash_seed, L=max(4 * ins.J[0], 16384), device=dev)
-        else:
-            L = 0 if gather_weight is None else choose_length(ins.I, ins.J, gather_weight)
-            plan = Plan(ins.I, ins.J, ins.D, ins.hash_seed, L=L, device=dev)
+        plan = plan_for(ins.kind, ins.I, ins.J, ins.D, ins.hash_seed, device=dev, gather_weight=gather_weight)
         items.append({"plan": plan, "kind": ins.kind, "U": U,
                       "out": torch.empty((ins.D, plan.Jt), dtype=torch.float32, device=dev)})
     return items

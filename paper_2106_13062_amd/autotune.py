@@ -52,6 +52,19 @@ def choose_length(I, J, gather_weight: float = 4.0, min_fft: int = 256, max_fft:
     return best_L
 
 
+def plan_for(kind: str, I, J, D: int, seed: int, device=None, gather_weight=None):
+    """Bound plan for one batch item.  CP items take the transform length of
+    the length model at `gather_weight` (None: the library planner's);
+    Kronecker items take a 16384-point (or longer) transform, which gives
+    their factor scatters 1024 threads."""
+    from .fcs import Plan
+    if kind == "kron":
+        L = max(4 * int(J[0]), 16384)
+    else:
+        L = 0 if gather_weight is None else choose_length(I, J, gather_weight)
+    return Plan(I, J, D, seed, L=L, device=device)
+
+
 def batch_signature(items) -> str:
     """Shape signature of a batch: plan shapes, ranks and kinds."""
     h = hashlib.sha1()

@@ -180,3 +180,46 @@ def test_batch_errors():
     b = Batch([], device=DEV)
     b.run(graph=True)
     b.run(graph=False)
+
+
+def test_batch_full_size_sampled_parity():
+    """The 4096-instance uneven batch (order 3-5, I_n up to 4096, R up to
+    256, J_n up to 2^13, every 16th a 256 x 256 Kronecker pair) built and
+    replayed from one graph as the benchmark does; sampled instances of every
+    FFT size class and both kinds against the FP64 oracle."""
+    from paper_2106_13062_amd.autotune import plan_for
+    insts = synth.batch_instances(4096)
+    items, hostF = [], {}
+    for k, (ins, F) in enumerate(synth.instance_inputs(insts)):
+        plan = plan_for(ins.kind, ins.I, ins.J, ins.D, ins.hash_seed, device=DEV, gather_weight=16.0)
+        U = [torch.from_numpy(m).to(DEV).t().contiguous() for m in F]
+        items.append({"plan": plan, "kind": ins.kind, "U": U})
+        hostF[k] = F
+    b = Batch(items, config={"tile_ffts": 32, "wg_per_cu": [0, 2, 0, 0, 0, 0, 2]}, device=DEV)
+    print(f"full batch: {len(items)} items, {b.tiles} tiles", flush=True)
+    b.run(graph=True)
+    b.run(graph=True)      # second replay: counters and queues reset themselves
+    torch.cuda.synchronize()
+    # one CP instance per FFT size class (the smallest rank, to keep the
+    # oracle quick) plus the largest-rank one, and two Kronecker instances
+    by_class = {}
+    for k, (ins, it) in enumerate(zip(insts, items)):
+        if ins.kind == "cp":
+            P = it["plan"].P
+            if P not in by_class or ins.R < insts[by_class[P]].R:
+                by_class[P] = k
+    sample = sorted(by_class.values())
+    sample.append(max((k for k, i in enumerate(insts) if i.kind == "cp"), key=lambda k: insts[k].R * len(insts[k].I)))
+    sample += [k for k, i in enumerate(insts) if i.kind == "kron"][:2]
+    for k in sample:
+        ins, plan = insts[k], items[k]["plan"]
+        got = items[k]["out"][0].cpu().numpy()
+        hs, ss = O.hash_tables(ins.hash_seed, 1, ins.I, ins.J)
+        if ins.kind == "kron":
+            A, B = (x.astype(np.float32).astype(np.float64) for x in hostF[k])
+            want = O.kron_fcs(A, B, hs[0], ss[0], ins.J)
+        else:
+            want = O.fcs_cp_fft(None, hostF[k], hs[0], ss[0], ins.J, plan.L)
+        print(f"instance {k} {ins.kind} I={ins.I} J={ins.J} R={ins.R} P={plan.P} Q={plan.Q}: "
+              f"{rel(got, want):.2e}", flush=True)
+        assert rel(got, want) <= TOL, (k, rel(got, want))
