@@ -11,12 +11,12 @@
 // from the largest magnitude among its first rows, adds round(x 2^F) with
 // ds_add_u32, and converts the bins back to float (exactly, by 2^-F) into
 // per-thread register accumulators at the end of every "period" of rows.
-//   * |round(x 2^F)| <= 2^22 - 1 for every element taken on this path; an
-//     element beyond (or a NaN / Inf) is added with a float atomic to the HBM
-//     sketch instead, so nothing is lost.
+//   * |round(x 2^F)| <= 2^21 - 1 for every element taken on this path (up to
+//     2-4x the sampled maximum); an element beyond (or a NaN / Inf) is added
+//     with a float atomic to the HBM sketch instead, so nothing is lost.
 //   * a row adds at most m0 elements to one bin, m0 the largest number of
 //     mode-0 indices sharing one h_0 value (computed when the plan is bound);
-//     a period of P rows with P * m0 <= 511 therefore keeps every bin below
+//     a period of P rows with P * m0 <= 1023 therefore keeps every bin below
 //     2^31 in magnitude: no overflow is possible.
 //   * the largest first-row magnitude maps into [2^19, 2^20), so the rounding
 //     step is at most 2^-19 of it: about 2e-6 relative error on a bin of
@@ -51,8 +51,8 @@ constexpr int SEG = 256;                // columns of a wave segment
 constexpr int NXCD = 8;
 constexpr int MAXACC = 32;              // register accumulators per thread
 constexpr int SCALE_TOP = 20;           // first-rows max maps below 2^20
-constexpr float QLIM = 4194302.0f;      // 2^22 - 2: larger |x 2^F| -> float path
-constexpr int ADD_BOUND = 511;          // P * m0 <= 511 keeps |bin| < 2^31
+constexpr float QLIM = 2097150.0f;      // 2^21 - 2: larger |x 2^F| -> float path
+constexpr int ADD_BOUND = 1023;         // P * m0 <= 1023 keeps |bin| < 2^31
 
 struct DenseArgs {
     const float *T;

@@ -103,14 +103,16 @@ def test_dense_unit_impulses():
 
 def test_dense_flush_period_with_many_collisions():
     """Fixed-point bins: a short row block (one column segment) whose mode-0
-    hash puts ~50 columns in one bin, and rows after the sampled leading rows
-    that are ~8x larger than the sample, all with the sign of sketch 0 so that
-    its bins add up without cancellation.  Every bin must stay exact."""
-    I, J, D, seed = (256, 64, 2), (6, 1, 8), 2, 77    # J_1 = 1: every row of a slab on the same bins
+    hash puts ~70 columns in one bin, and rows after the sampled leading rows
+    that are 3.9x larger than the sample (just inside the fixed-point range),
+    all with the sign of sketch 0 so that its bins add up without
+    cancellation.  A flush period of more rows than the bound allows would
+    overflow a bin; every bin must stay exact."""
+    I, J, D, seed = (256, 64, 2), (4, 1, 8), 2, 77    # J_1 = 1: every row of a slab on the same bins
     hs, ss = O.hash_tables(seed, D, I, J)
     s0, s1, s2 = (ss[0][n].astype(np.float64) for n in range(3))
     sign = s0[:, None, None] * s1[None, :, None] * s2[None, None, :]
-    mag = np.full(I, 7.9)
+    mag = np.full(I, 3.9)
     mag[:, :16, :] = 1.0                     # the rows the scale is taken from
     T = O.vec(sign * mag).astype(np.float32)
     plan = Plan(I, J, D, seed, device=DEV)
