@@ -17,7 +17,8 @@
 //   * a row adds at most m0 elements to one bin, m0 the largest number of
 //     mode-0 indices sharing one h_0 value (computed when the plan is bound);
 //     a period of P rows with P * m0 <= 1023 therefore keeps every bin below
-//     2^31 in magnitude: no overflow is possible.
+//     2^31 in magnitude: no overflow is possible.  Plans with m0 > 255
+//     (a period shorter than 4 rows) take the HBM float-atomic kernel.
 //   * the largest first-row magnitude maps into [2^19, 2^20), so the rounding
 //     step is at most 2^-19 of it: about 2e-6 relative error on a bin of
 //     Gaussian data, against 1e-5 allowed.  Integer-valued data with small
@@ -31,8 +32,14 @@
 //    the rows it visits; its lanes keep the LDS byte address of bin h_0(i_0)
 //    and the sign of s_0(i_0) of every sketch of the group in registers.  Per
 //    element: one scale, one range test, one v_cvt_rpi (round); per element
-//    and sketch: one v_mul_i32_i24 (column sign), one v_add (address) and
-//    one ds_add_u32 or ds_sub_u32 (the row sign, uniform per wave).
+//    and sketch: one v_mul_i32_i24 (column sign), half a 64-bit add (the
+//    addresses of two sketches share one v_lshl_add_u64) and one ds_add_u32
+//    or ds_sub_u32 (the row sign, uniform per wave).
+//  * Each wave keeps four row loads in flight (rows k+1..k+4 while row k is
+//    added); every row issues exactly one load, so each wait is "at most
+//    three younger loads outstanding".  The row offsets and signs of a flush
+//    period are computed into a small LDS table during the previous flush,
+//    so the row loop issues no other memory loads.
 //  * When N >= 2 a workgroup's rows share the last-mode index, so its bins lie
 //    in h_{N-1}(i_{N-1}) + [0, J~ - J_{N-1} + 1) and only that window is held
 //    (the last mode's sign is applied at the flush).  Sketches are split into
@@ -53,6 +60,7 @@ constexpr int MAXACC = 32;              // register accumulators per thread
 constexpr int SCALE_TOP = 20;           // first-rows max maps below 2^20
 constexpr float QLIM = 2097150.0f;      // 2^21 - 2: larger |x 2^F| -> float path
 constexpr int ADD_BOUND = 1023;         // P * m0 <= 1023 keeps |bin| < 2^31
+constexpr size_t ROWTAB_BYTES = 16 * ADD_BOUND;   // row table of one flush period (<= ADD_BOUND rows)
 
 struct DenseArgs {
     const float *T;
@@ -121,7 +129,7 @@ __device__ inline void dense_block_map(const DenseArgs &a, int64_t bid, int64_t 
 template <bool VEC4, bool FULL>
 __device__ __forceinline__ void load_seg(const float *row, int lane, const bool (&valid)[4], float (&x)[4]) {
     if (FULL && VEC4) {
-        const float4 q = *reinterpret_cast<const float4 *>(row + lane * 4);
+        const float4 q = reinterpret_cast<const float4 *>(row)[lane];
         x[0] = q.x; x[1] = q.y; x[2] = q.z; x[3] = q.w;
     } else {
 #pragma unroll
@@ -129,13 +137,22 @@ __device__ __forceinline__ void load_seg(const float *row, int lane, const bool 
     }
 }
 
+// The LDS addresses of one element in two sketches of a pair sit in the low
+// and high halves of a 64-bit register; one 64-bit add of the two uniform
+// row offsets forms both (every address is below 2^18, so no carry crosses
+// the halves).
+__device__ __forceinline__ uint64_t add_pair(uint64_t v, uint64_t s) {
+    uint64_t r;
+    asm("v_lshl_add_u64 %0, %1, 0, %2" : "=v"(r) : "v"(v), "s"(s));
+    return r;
+}
+
 // Out-of-range or non-finite entries of one row segment: float atomics into
 // the HBM sketch, with every sign including the slab's last-mode sign.
 template <int DG, bool CHECK>
 __device__ __forceinline__ void scatter_slow(const DenseArgs &a, uint32_t qaddr, const float (&x)[4], float scale,
-                                             int d0, const uint32_t (&A)[DG][4], const int (&S)[DG][4],
-                                             const bool (&valid)[4], const uint32_t (&C)[DG],
-                                             const uint32_t (&R)[DG], const int (&base)[DG],
+                                             int d0, const uint64_t (&A2)[(DG + 1) / 2][4], const int (&S)[DG][4],
+                                             const bool (&valid)[4], const uint32_t (&C)[DG], const int (&base)[DG],
                                              const uint32_t (&wsign)[DG]) {
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
@@ -143,8 +160,9 @@ __device__ __forceinline__ void scatter_slow(const DenseArgs &a, uint32_t qaddr,
         if ((!CHECK || valid[e]) && !(fabsf(xe * scale) < QLIM)) {
 #pragma unroll
             for (int d = 0; d < DG; ++d) {
-                const int bin = (int)((A[d][e] + C[d] - qaddr) / 4u) - d * a.W;
-                const uint32_t sg = (S[d][e] < 0 ? FCS_S_BIT : 0u) ^ R[d] ^ wsign[d];
+                const uint32_t ad = (d & 1) ? (uint32_t)(A2[d >> 1][e] >> 32) : (uint32_t)A2[d >> 1][e];
+                const int bin = (int)((ad + (C[d] & FCS_H_MASK) - qaddr) / 4u) - d * a.W;
+                const uint32_t sg = (S[d][e] < 0 ? FCS_S_BIT : 0u) ^ (C[d] & FCS_S_BIT) ^ wsign[d];
                 unsafeAtomicAdd(a.out + (int64_t)(d0 + d) * a.Jt + base[d] + bin,
                                 __uint_as_float(__float_as_uint(xe) ^ sg));
             }
@@ -152,150 +170,186 @@ __device__ __forceinline__ void scatter_slow(const DenseArgs &a, uint32_t qaddr,
     }
 }
 
-// Add one row segment (4 values per lane) to the DG fixed-point windows.
-// Each value is scaled and rounded once (v_cvt_rpi); the column sign of
-// every sketch is a 24-bit integer multiply by +-1 and the row sign, uniform
-// across the wave, selects ds_sub_u32 instead of ds_add_u32.  A wave with an
-// out-of-range element in the row takes the float path for those elements
-// and adds zero for them to the bins.
-template <int DG, bool CHECK>
-__device__ __forceinline__ void scatter_seg(const DenseArgs &a, uint32_t qaddr, const float (&x)[4], float scale,
-                                            int d0, const uint32_t (&A)[DG][4], const int (&S)[DG][4],
-                                            const bool (&valid)[4], const uint32_t (&C)[DG],
-                                            const uint32_t (&R)[DG], const int (&base)[DG],
-                                            const uint32_t (&wsign)[DG]) {
+// Add one row segment (4 values per lane, in `buf`) to the DG fixed-point
+// windows, then reuse `buf` for the load of row `next`.  Each value is scaled
+// and rounded once (v_cvt_rpi); the column sign of every sketch is a 24-bit
+// integer multiply by +-1 and the row sign, uniform across the wave, selects
+// ds_sub_u32 instead of ds_add_u32.  A wave with an out-of-range element in
+// the row takes the float path for those elements and adds zero for them to
+// the bins.  C holds the row's words (byte offset | sign bit) per sketch.
+template <int DG, bool VEC4, bool FULL>
+__device__ __forceinline__ void scatter_row(const DenseArgs &a, uint32_t qaddr, float (&buf)[4], const float *next,
+                                            float scale, int d0, int lane, const uint64_t (&A2)[(DG + 1) / 2][4],
+                                            const int (&S)[DG][4], const bool (&valid)[4], const uint32_t (&C)[DG],
+                                            const int (&base)[DG], const uint32_t (&wsign)[DG], bool process) {
+    constexpr int DP = (DG + 1) / 2;
+    constexpr bool CHECK = !FULL;
     int q[4];
-    bool slow = false;
+    if (process) {
+        bool slow = false;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const float xs = x[e] * scale;
-        slow |= !(fabsf(xs) < QLIM) && (!CHECK || valid[e]);   // NaN / Inf too
-        q[e] = cvt_rpi(xs);            // saturating; zeroed below when out of range
+        for (int e = 0; e < 4; ++e) {
+            const float xs = buf[e] * scale;
+            slow |= !(fabsf(xs) < QLIM) && (!CHECK || valid[e]);   // NaN / Inf too
+            q[e] = cvt_rpi(xs);            // saturating; zeroed below when out of range
+        }
+        if (__builtin_expect(__builtin_amdgcn_ballot_w64(slow) != 0, 0)) {
+            scatter_slow<DG, CHECK>(a, qaddr, buf, scale, d0, A2, S, valid, C, base, wsign);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) q[e] = (fabsf(buf[e] * scale) < QLIM) ? q[e] : 0;
+        }
     }
-    if (__builtin_expect(__builtin_amdgcn_ballot_w64(slow) != 0, 0)) {
-        scatter_slow<DG, CHECK>(a, qaddr, x, scale, d0, A, S, valid, C, R, base, wsign);
+    // the load is issued whether or not the row is processed, so every
+    // group of 4 rows issues exactly 4 loads (in-order waits stay exact)
+    load_seg<VEC4, FULL>(next, lane, valid, buf);
+    if (!process) return;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) q[e] = (fabsf(x[e] * scale) < QLIM) ? q[e] : 0;
-    }
+    for (int p = 0; p < DP; ++p) {
+        const uint32_t lo = C[2 * p] & FCS_H_MASK;
+        const uint32_t hi = C[2 * p + 1 < DG ? 2 * p + 1 : 2 * p] & FCS_H_MASK;
+        const uint64_t cc = (uint64_t)lo | ((uint64_t)hi << 32);
+        uint64_t ad[4];
 #pragma unroll
-    for (int d = 0; d < DG; ++d) {
-        if (R[d]) {
+        for (int e = 0; e < 4; ++e) ad[e] = add_pair(A2[p][e], cc);
 #pragma unroll
-            for (int e = 0; e < 4; ++e)
-                if (!CHECK || valid[e]) lds_sub(A[d][e] + C[d], (uint32_t)mul_i24(q[e], S[d][e]));
-        } else {
+        for (int h = 0; h < 2 && 2 * p + h < DG; ++h) {
+            const int d = 2 * p + h;
+            if (C[d] & FCS_S_BIT) {
 #pragma unroll
-            for (int e = 0; e < 4; ++e)
-                if (!CHECK || valid[e]) lds_add(A[d][e] + C[d], (uint32_t)mul_i24(q[e], S[d][e]));
+                for (int e = 0; e < 4; ++e)
+                    if (!CHECK || valid[e])
+                        lds_sub(h ? (uint32_t)(ad[e] >> 32) : (uint32_t)ad[e], (uint32_t)mul_i24(q[e], S[d][e]));
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (!CHECK || valid[e])
+                        lds_add(h ? (uint32_t)(ad[e] >> 32) : (uint32_t)ad[e], (uint32_t)mul_i24(q[e], S[d][e]));
+            }
         }
     }
 }
 
-// Row offsets and signs of 64 consecutive rows of a wave, one row per lane:
-// lane j holds, for every sketch of the group, (byte offset of row
-// rb + j * wps in the window) | (row sign bit).  Rows are fetched 64 at a
-// time and broadcast with v_readlane, so the hot loop issues no per-row
-// table loads.  The chunk's first row rb is decoded once (uniform); each lane
-// adds its offset j * wps < 1024 with 32-bit carries.
+// Row words of a flush period, kept in LDS after the bins: for each of the
+// `cnt` block rows from r (global row index) on, 4 words (one per sketch of
+// the group, unused ones zero): (byte offset of the row in the window) |
+// (row sign bit), the row offset being sum_n h_n(i_n) over the modes that
+// vary along the block's rows.  Filled by the whole workgroup between the
+// barriers of a period flush, so the row loop issues no table loads.
 template <int DG, int NV>
-__device__ __forceinline__ void row_words(const DenseArgs &a, int d0, int64_t rb, int lane, int wps, bool live,
-                                          uint32_t (&CR)[DG]) {
-    int idx[NV > 0 ? NV : 1];
-    {
-        int64_t r = rb;
-        uint32_t carry = (uint32_t)(lane * wps);
+__device__ __forceinline__ void fill_rowtab(const DenseArgs &a, int d0, uint32_t *rowtab, int64_t r, int cnt) {
+    for (int j = threadIdx.x; j < cnt; j += DS_THREADS) {
+        int64_t rem = r + j;
+        int idx[NV > 0 ? NV : 1];
 #pragma unroll
         for (int n = 0; n < NV; ++n) {
-            const uint32_t In = (uint32_t)a.I[n + 1];
-            const uint32_t b = (uint32_t)(r % In);
-            r /= In;
-            const uint32_t t = b + carry;
-            if (t < In) {
-                idx[n] = (int)t;
-                carry = 0;
-            } else {
-                idx[n] = (int)(t % In);
-                carry = t / In;
+            const int64_t In = a.I[n + 1];
+            idx[n] = (int)(rem % In);
+            rem /= In;
+        }
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            uint32_t c = 0, sg = 0;
+            if (d < DG) {
+#pragma unroll
+                for (int n = 0; n < NV; ++n) {
+                    const uint32_t w = a.tab[(int64_t)(d0 + d) * a.sumI + a.off[n + 1] + idx[n]];
+                    c += (w & FCS_H_MASK) * 4u;
+                    sg ^= w & FCS_S_BIT;
+                }
             }
+            rowtab[j * 4 + d] = c | sg;
         }
-    }
-#pragma unroll
-    for (int d = 0; d < DG; ++d) {
-        uint32_t c = 0, sg = 0;
-#pragma unroll
-        for (int n = 0; n < NV; ++n) {
-            const uint32_t w = live ? a.tab[(int64_t)(d0 + d) * a.sumI + a.off[n + 1] + idx[n]] : 0u;
-            c += (w & FCS_H_MASK) * 4u;
-            sg ^= w & FCS_S_BIT;
-        }
-        CR[d] = c | sg;
     }
 }
 
 // One wave's rows r_first + k * wps (k < nk) of one column segment, in flush
-// periods of pk rows.  Two row loads are in flight (ping-pong buffers) and
-// stay in flight across the period barriers.  Every wave of the workgroup
-// calls this with the same period count so all reach every barrier.
+// periods of pk rows.  Four row loads are in flight: row k + 4 is loaded into
+// the buffer of row k as soon as row k is rounded.  Loads past the last row
+// re-read it, so every row issues exactly one load and the wait for a row is
+// always "at most three younger loads outstanding".  Every wave of the
+// workgroup calls this with the same period count so all reach every barrier.
 template <int DG, int NV, bool VEC4, bool FULL>
-__device__ __forceinline__ void wave_rows(const DenseArgs &a, uint32_t *qbins, float (&acc)[MAXACC], float scale,
-                                          float inv, int d0, int seg, int lane, bool active, int64_t r_first,
-                                          int64_t nk, int wps, int64_t pk, int64_t nperiods, const int (&base)[DG],
-                                          const uint32_t (&wsign)[DG]) {
+__device__ __forceinline__ void wave_rows(const DenseArgs &a, uint32_t *qbins, uint32_t *rowtab, float (&acc)[MAXACC],
+                                          float scale, float inv, int d0, int seg, int lane, bool active, int64_t r0,
+                                          int64_t nrows, int rl, int nk, int wps, int pk, int nperiods,
+                                          const int (&base)[DG], const uint32_t (&wsign)[DG]) {
+    const int64_t r_first = r0 + rl;
+    constexpr int DP = (DG + 1) / 2;
     const int W = a.W;
     const uint32_t qaddr = lds_addr(qbins);
-    uint32_t A[DG][4];
+    uint64_t A2[DP][4];
     int S[DG][4];
     bool valid[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
         const int64_t col = (int64_t)seg * SEG + lane * 4 + e;
         valid[e] = active && col < a.I0;
+        uint32_t Ad[DG];
 #pragma unroll
         for (int d = 0; d < DG; ++d) {
             const uint32_t p = valid[e] ? a.tab[(int64_t)(d0 + d) * a.sumI + col] : 0u;
-            A[d][e] = qaddr + (uint32_t)((d * W + (int)(p & FCS_H_MASK)) * 4);
+            Ad[d] = qaddr + (uint32_t)((d * W + (int)(p & FCS_H_MASK)) * 4);
             S[d][e] = (p & FCS_S_BIT) ? -1 : 1;
         }
+#pragma unroll
+        for (int p = 0; p < DP; ++p)
+            A2[p][e] = (uint64_t)Ad[2 * p] | ((uint64_t)Ad[2 * p + 1 < DG ? 2 * p + 1 : 2 * p] << 32);
     }
     const float *Tseg = a.T + (int64_t)seg * SEG;
-    const int64_t rstride = (int64_t)wps * a.I0;
-    // b0 holds the even rows k, b1 the odd ones; row k + 2 is loaded into
-    // the buffer of row k as soon as row k is consumed
-    float b0[4], b1[4];
+    const int64_t I0 = a.I0;
+    auto rowp = [&](int k) { return Tseg + (r_first + (int64_t)min(k, nk - 1) * wps) * I0; };
+    float b0[4], b1[4], b2[4], b3[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
         b0[e] = 0.f;
         b1[e] = 0.f;
+        b2[e] = 0.f;
+        b3[e] = 0.f;
     }
-    if (active && nk > 0) load_seg<VEC4, FULL>(Tseg + r_first * a.I0, lane, valid, b0);
-    if (active && nk > 1) load_seg<VEC4, FULL>(Tseg + r_first * a.I0 + rstride, lane, valid, b1);
+    if (active && nk > 0) {
+        load_seg<VEC4, FULL>(rowp(0), lane, valid, b0);
+        load_seg<VEC4, FULL>(rowp(1), lane, valid, b1);
+        load_seg<VEC4, FULL>(rowp(2), lane, valid, b2);
+        load_seg<VEC4, FULL>(rowp(3), lane, valid, b3);
+    }
+    // lane j holds the words of wave row k0 + j (64 rows of the period at a
+    // time, read from the period's row table and broadcast with v_readlane)
     uint32_t CR[DG];
-    row_words<DG, NV>(a, d0, r_first, lane, wps, active && lane < nk, CR);
-
-    auto row = [&](int64_t k, float (&buf)[4]) {
-        uint32_t C[DG], R[DG];
+    auto refresh = [&](int k0, int kb, int ke) {
+        const bool live = k0 + lane < ke;
+        const int j = rl + (k0 + lane - kb) * wps;
 #pragma unroll
-        for (int d = 0; d < DG; ++d) {
-            const uint32_t w = __builtin_amdgcn_readlane(CR[d], (int)(k & 63));
-            C[d] = w & FCS_H_MASK;
-            R[d] = w & FCS_S_BIT;
-        }
-        float x[4];
+        for (int d = 0; d < DG; ++d) CR[d] = live ? rowtab[j * 4 + d] : 0u;
+        // take the wait for these reads here, once per 64 rows, so that the
+        // row loop does not wait for its own atomics before v_readlane
 #pragma unroll
-        for (int e = 0; e < 4; ++e) x[e] = buf[e];
-        if (k + 2 < nk) load_seg<VEC4, FULL>(Tseg + (r_first * a.I0 + (k + 2) * rstride), lane, valid, buf);
-        scatter_seg<DG, !FULL>(a, qaddr, x, scale, d0, A, S, valid, C, R, base, wsign);
+        for (int d = 0; d < DG; ++d) asm volatile("" : "+v"(CR[d]));
+    };
+    auto row = [&](int k, int k0, float (&buf)[4], bool process) {
+        uint32_t C[DG];
+#pragma unroll
+        for (int d = 0; d < DG; ++d) C[d] = process ? __builtin_amdgcn_readlane(CR[d], k - k0) : 0u;
+        scatter_row<DG, VEC4, FULL>(a, qaddr, buf, rowp(k + 4), scale, d0, lane, A2, S, valid, C, base, wsign,
+                                    process);
     };
 
-    for (int64_t p = 0; p < nperiods; ++p) {
-        const int64_t kb = p * pk;
-        const int64_t ke = min(kb + pk, active ? nk : (int64_t)0);
-        int64_t k = kb;
-        if (k < ke && (k & 1)) row(k++, b1);     // odd k: never a 64-row boundary
-        for (; k < ke; k += 2) {
-            if ((k & 63) == 0 && k > 0) row_words<DG, NV>(a, d0, r_first + k * wps, lane, wps, k + lane < nk, CR);
-            row(k, b0);
-            if (k + 1 < ke) row(k + 1, b1);
+    // pk is a multiple of 4, so every period starts on buffer b0; only the
+    // wave's last group can hold fewer than 4 rows
+    int k = 0;
+    for (int p = 0; p < nperiods; ++p) {
+        const int kb = p * pk;
+        const int ke = active ? min(kb + pk, nk) : 0;
+        int k0 = k;
+        if (k < ke) refresh(k0, kb, ke);
+        for (; k < ke; k += 4) {
+            if (k - k0 == 64) {
+                k0 = k;
+                refresh(k0, kb, ke);
+            }
+            row(k, k0, b0, true);
+            row(k + 1, k0, b1, k + 1 < ke);
+            row(k + 2, k0, b2, k + 2 < ke);
+            row(k + 3, k0, b3, k + 3 < ke);
         }
         __syncthreads();
         // period flush: integer bins -> float register accumulators (exact
@@ -307,6 +361,10 @@ __device__ __forceinline__ void wave_rows(const DenseArgs &a, uint32_t *qbins, f
                 acc[m] += (float)(int)qbins[kq] * inv;
                 qbins[kq] = 0u;
             }
+        }
+        if (p + 1 < nperiods) {
+            const int64_t jb = (int64_t)(p + 1) * pk * wps;
+            fill_rowtab<DG, NV>(a, d0, rowtab, r0 + jb, (int)min<int64_t>((int64_t)pk * wps, nrows - jb));
         }
         __syncthreads();
     }
@@ -367,8 +425,17 @@ __global__ __launch_bounds__(DS_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
         const int64_t r = r0 + (wave % nrows);
         const int64_t c0 = (int64_t)s0 * SEG;
         const int64_t c1 = min<int64_t>(min<int64_t>((int64_t)s1 * SEG, a.I0), c0 + 4096);
+        const float *rowp = a.T + r * a.I0;
         float m = 0.f;
-        for (int64_t c = c0 + lane; c < c1; c += 64) m = fmaxf(m, fabsf(a.T[r * a.I0 + c]));
+        // 16 independent loads per pass (one memory latency per 1024
+        // columns); indices past the end re-read the last column
+        for (int64_t c = c0 + lane; c < c1; c += 1024) {
+            float v[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) v[u] = rowp[min<int64_t>(c + u * 64, c1 - 1)];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) m = fmaxf(m, fabsf(v[u]));
+        }
         // NaN / Inf in the sample are ignored here; they take the float path
         if (!(m <= 3.0e38f)) m = 0.f;
 #pragma unroll
@@ -380,7 +447,21 @@ __global__ __launch_bounds__(DS_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
 #pragma unroll
     for (int w = 0; w < DS_WAVES; ++w) M0 = fmaxf(M0, __uint_as_float(qbins[w]));
     __syncthreads();
+    // each wave owns at most one (segment, row lane) of the block; waves
+    // per segment at most period / 4 so that a multiple of 4 rows per wave
+    // fits a flush period (pk * wps <= period)
+    const int wps = max(1, min(DS_WAVES / nseg, a.period / 4));
+    const int64_t nrows = r1 - r0;
+    const bool active = wave < nseg * wps;
+    const int seg = s0 + (active ? wave % nseg : 0);
+    const int rl = active ? wave / nseg : 0;
+    const int nk = (active && rl < nrows) ? (int)((nrows - rl + wps - 1) / wps) : 0;
+    const int pk = (a.period / wps) & ~3;                // >= 4, a multiple of 4
+    const int nperiods = (int)((fcs_ceil_div_dev(nrows, wps) + pk - 1) / pk);
+    // the row table of the first period sits after the bins (16-byte aligned)
+    uint32_t *rowtab = qbins + ((DG * W + 3) & ~3);
     for (int k = threadIdx.x; k < DG * W; k += DS_THREADS) qbins[k] = 0u;
+    fill_rowtab<DG, NV>(a, d0, rowtab, r0, (int)min<int64_t>((int64_t)pk * wps, nrows));
     __syncthreads();
     int F = SCALE_TOP - 1;
     if (M0 > 0.f) F = SCALE_TOP - __builtin_amdgcn_frexp_expf(M0);
@@ -392,19 +473,9 @@ __global__ __launch_bounds__(DS_THREADS) __attribute__((amdgpu_waves_per_eu(2, 2
 #pragma unroll
     for (int m = 0; m < MAXACC; ++m) acc[m] = 0.f;
 
-    // each wave owns at most one (segment, row lane) of the block
-    // waves per segment; at most `period` so that pk * wps <= period
-    const int wps = max(1, min(DS_WAVES / nseg, a.period));
-    const int64_t nrows = r1 - r0;
-    const bool active = wave < nseg * wps;
-    const int seg = s0 + (active ? wave % nseg : 0);
-    const int rl = active ? wave / nseg : 0;
-    const int64_t nk = (active && rl < nrows) ? (nrows - rl + wps - 1) / wps : 0;
-    const int64_t pk = a.period / wps;                   // >= 1
-    const int64_t nperiods = (fcs_ceil_div_dev(nrows, wps) + pk - 1) / pk;
     // FULL kernels are launched only when every segment is complete
-    wave_rows<DG, NV, VEC4, FULL>(a, qbins, acc, scale, inv, d0, seg, lane, active, r0 + rl, nk, wps, pk, nperiods,
-                                  base, wsign);
+    wave_rows<DG, NV, VEC4, FULL>(a, qbins, rowtab, acc, scale, inv, d0, seg, lane, active, r0, nrows, rl, nk, wps,
+                                  pk, nperiods, base, wsign);
 
     // add the window to the HBM sketch, with the slab's last-mode sign
 #pragma unroll
@@ -467,11 +538,12 @@ DenseLaunch plan_dense(const fcs_plan *p) {
     for (int n = 1; n < p->N; ++n) rows *= p->I[n];
     const int64_t I0 = p->I[0];
     L.segs = (int)fcs_ceil_div(I0, SEG);
-    const size_t budget = std::min<size_t>(FCS_LDS_BYTES - 1024, (size_t)MAXACC * DS_THREADS * 4);
+    // bins of DG windows plus the row table of one flush period
+    const size_t budget = std::min<size_t>(FCS_LDS_BYTES - 1024 - ROWTAB_BYTES, (size_t)MAXACC * DS_THREADS * 4);
     const int64_t total = rows * I0;
     // windowed: a row block never spans two values of the last mode
     // a single row may not add more than ADD_BOUND elements to one bin
-    if (p->m0 > ADD_BOUND) return L;
+    if (4 * p->m0 > ADD_BOUND) return L;
     if (p->N >= 2) {
         const int64_t Wwin = p->Jt - p->J[p->N - 1] + 1;
         const int64_t slab_rows = rows / p->I[p->N - 1];
@@ -772,7 +844,7 @@ extern "C" fcs_status fcs_sketch_dense(fcs_plan_t p, const float *T, float *out,
         a.d_first = pass == 0 ? 0 : full_groups * L.dg;
         const int64_t grid64 = blocks_rounded * groups;
         if (grid64 > INT32_MAX) FCS_FAIL(FCS_EUNSUPPORTED, "grid too large");
-        const size_t lds = (size_t)dg * (size_t)L.W * sizeof(uint32_t);
+        const size_t lds = (((size_t)dg * (size_t)L.W + 3) & ~(size_t)3) * sizeof(uint32_t) + 16 * (size_t)a.period;
         switch (dg) {
         case 1: launch_dense<1>(a, vec4, lds, (unsigned)grid64, s); break;
         case 2: launch_dense<2>(a, vec4, lds, (unsigned)grid64, s); break;
