@@ -52,8 +52,23 @@ struct fcs_plan {
     // sketches (bounds the additions one row makes to one bin); INT32_MAX
     // when too large to evaluate on the host
     int m0 = INT32_MAX;
+    // lane order of the dense scatter: for each group of sketches and each
+    // 256-column segment, the 16-byte column block each of the 64 lanes of a
+    // wave loads (D x segs x 64 bytes; absent when perm_bytes == 0)
+    // (computed on the first dense sketch of the plan, see perm_ready)
+    size_t perm_off = 0, perm_bytes = 0;
+    const uint8_t *perm = nullptr;
+    bool perm_ready = false;
     bool bound = false;
 };
+
+// dense scatter lane order (scatter.hip): bytes reserved in the plan layout,
+// and the search that fills them from the host's mode-0 hash values
+// (h0[d * I_0 + i] = h_0 of sketch d); perm has perm_bytes entries
+size_t fcs_dense_perm_bytes(const fcs_plan *p);
+void fcs_dense_lane_order(const fcs_plan *p, const uint32_t *h0, uint8_t *perm);
+// h_0 of every sketch on the host (plan.hip), h0[d * I_0 + i]
+void fcs_mode0_hashes(const fcs_plan *p, uint32_t *h0);
 
 // error reporting ----------------------------------------------------------
 void fcs_set_error(const char *fmt, ...);

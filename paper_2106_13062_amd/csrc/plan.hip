@@ -236,6 +236,9 @@ extern "C" fcs_status fcs_plan_create(const fcs_plan_desc *desc, fcs_plan_t *out
     }
     tmp.inv_off = cur;
     cur = align256(cur + (size_t)tmp.D * (size_t)tmp.iblock * sizeof(int32_t));
+    tmp.perm_off = cur;
+    tmp.perm_bytes = fcs_dense_perm_bytes(&tmp);
+    cur = align256(cur + tmp.perm_bytes);
     tmp.total = cur;
     fcs_plan *p = new (std::nothrow) fcs_plan(tmp);
     if (!p) FCS_FAIL(FCS_ENOMEM, "host allocation of the plan failed");
@@ -290,6 +293,17 @@ static fcs_status build_inverse(const fcs_plan *p, int32_t *dev_inv, hipStream_t
     FCS_HIP_CHECK(hipMemcpyAsync(dev_inv, host.data(), host.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
     FCS_HIP_CHECK(hipStreamSynchronize(s));
     return FCS_OK;
+}
+
+void fcs_mode0_hashes(const fcs_plan *p, uint32_t *h0) {
+    const uint64_t sm = sm64_mix(p->seed);
+    for (int d = 0; d < p->D; ++d) {
+        const uint64_t key = sm64_mix(sm + ((uint64_t)d << 16) + 0u);
+        for (int64_t i = 0; i < p->I[0]; ++i) {
+            const uint64_t y = sm64_mix(key + (uint64_t)i);
+            h0[(size_t)d * p->I[0] + i] = (uint32_t)(((y >> 32) * (uint64_t)p->J[0]) >> 32);
+        }
+    }
 }
 
 // Largest multiplicity of h_0 values over all sketches, evaluated with the
@@ -348,6 +362,8 @@ extern "C" fcs_status fcs_plan_bind(fcs_plan_t p, void *dev_tables, void *stream
         fcs_status st = build_inverse(p, (int32_t *)(base + p->inv_off), s);
         if (st != FCS_OK) return st;
     }
+    p->perm = p->perm_bytes ? (const uint8_t *)(base + p->perm_off) : nullptr;
+    p->perm_ready = false;
     p->inv = (const int32_t *)(base + p->inv_off);
     p->tab = (const uint32_t *)(base + p->tab_off);
     p->twP = (const float2 *)(base + p->twP_off);

@@ -49,12 +49,16 @@
 #include "fcs_internal.h"
 
 #include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <vector>
 
 namespace {
 
 constexpr int DS_THREADS = 1024;        // 16 waves
 constexpr int DS_WAVES = DS_THREADS / 64;
 constexpr int SEG = 256;                // columns of a wave segment
+constexpr int GSEG = 4;                 // segments per lane-order set (1024 columns)
 constexpr int NXCD = 8;
 constexpr int MAXACC = 32;              // register accumulators per thread
 constexpr int SCALE_TOP = 20;           // first-rows max maps below 2^20
@@ -87,6 +91,8 @@ struct DenseArgs {
     int segs_per_block;
     int period;              // rows per flush period
     int nrow_modes;          // modes 1..nrow_modes vary along a block's rows
+    int dg_full;             // sketches per group of the first pass
+    const uint8_t *perm;     // lane order per (group, segment); null: identity
 };
 
 // 24-bit signed multiply (|a| < 2^22, b = +-1 here): one VALU op, with no
@@ -127,13 +133,14 @@ __device__ inline void dense_block_map(const DenseArgs &a, int64_t bid, int64_t 
 }
 
 template <bool VEC4, bool FULL>
-__device__ __forceinline__ void load_seg(const float *row, int lane, const bool (&valid)[4], float (&x)[4]) {
+// the 4 columns of 16-byte block `blk` of a row segment
+__device__ __forceinline__ void load_seg(const float *row, int blk, const bool (&valid)[4], float (&x)[4]) {
     if (FULL && VEC4) {
-        const float4 q = reinterpret_cast<const float4 *>(row)[lane];
+        const float4 q = reinterpret_cast<const float4 *>(row)[blk];
         x[0] = q.x; x[1] = q.y; x[2] = q.z; x[3] = q.w;
     } else {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) x[e] = (FULL || valid[e]) ? row[lane * 4 + e] : 0.f;
+        for (int e = 0; e < 4; ++e) x[e] = (FULL || valid[e]) ? row[blk * 4 + e] : 0.f;
     }
 }
 
@@ -179,7 +186,7 @@ __device__ __forceinline__ void scatter_slow(const DenseArgs &a, uint32_t qaddr,
 // the bins.  C holds the row's words (byte offset | sign bit) per sketch.
 template <int DG, bool VEC4, bool FULL>
 __device__ __forceinline__ void scatter_row(const DenseArgs &a, uint32_t qaddr, float (&buf)[4], const float *next,
-                                            float scale, int d0, int lane, const uint64_t (&A2)[(DG + 1) / 2][4],
+                                            float scale, int d0, int blk, const uint64_t (&A2)[(DG + 1) / 2][4],
                                             const int (&S)[DG][4], const bool (&valid)[4], const uint32_t (&C)[DG],
                                             const int (&base)[DG], const uint32_t (&wsign)[DG], bool process) {
     constexpr int DP = (DG + 1) / 2;
@@ -201,7 +208,7 @@ __device__ __forceinline__ void scatter_row(const DenseArgs &a, uint32_t qaddr, 
     }
     // the load is issued whether or not the row is processed, so every
     // group of 4 rows issues exactly 4 loads (in-order waits stay exact)
-    load_seg<VEC4, FULL>(next, lane, valid, buf);
+    load_seg<VEC4, FULL>(next, blk, valid, buf);
     if (!process) return;
 #pragma unroll
     for (int p = 0; p < DP; ++p) {
@@ -280,9 +287,14 @@ __device__ __forceinline__ void wave_rows(const DenseArgs &a, uint32_t *qbins, u
     uint64_t A2[DP][4];
     int S[DG][4];
     bool valid[4];
+    // the 16-byte column block this lane loads: with a lane order, any block
+    // of the segment's set of GSEG segments (1024 columns), chosen at bind to
+    // spread LDS banks; without one, block `lane` of its own segment
+    const int64_t set_col = a.perm ? (int64_t)(seg / GSEG) * (GSEG * SEG) : (int64_t)seg * SEG;
+    const int pb = a.perm ? (int)a.perm[((int64_t)(d0 / a.dg_full) * a.segs + seg) * 64 + lane] : lane;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-        const int64_t col = (int64_t)seg * SEG + lane * 4 + e;
+        const int64_t col = set_col + pb * 4 + e;
         valid[e] = active && col < a.I0;
         uint32_t Ad[DG];
 #pragma unroll
@@ -295,7 +307,7 @@ __device__ __forceinline__ void wave_rows(const DenseArgs &a, uint32_t *qbins, u
         for (int p = 0; p < DP; ++p)
             A2[p][e] = (uint64_t)Ad[2 * p] | ((uint64_t)Ad[2 * p + 1 < DG ? 2 * p + 1 : 2 * p] << 32);
     }
-    const float *Tseg = a.T + (int64_t)seg * SEG;
+    const float *Tseg = a.T + set_col;
     const int64_t I0 = a.I0;
     auto rowp = [&](int k) { return Tseg + (r_first + (int64_t)min(k, nk - 1) * wps) * I0; };
     float b0[4], b1[4], b2[4], b3[4];
@@ -307,10 +319,10 @@ __device__ __forceinline__ void wave_rows(const DenseArgs &a, uint32_t *qbins, u
         b3[e] = 0.f;
     }
     if (active && nk > 0) {
-        load_seg<VEC4, FULL>(rowp(0), lane, valid, b0);
-        load_seg<VEC4, FULL>(rowp(1), lane, valid, b1);
-        load_seg<VEC4, FULL>(rowp(2), lane, valid, b2);
-        load_seg<VEC4, FULL>(rowp(3), lane, valid, b3);
+        load_seg<VEC4, FULL>(rowp(0), pb, valid, b0);
+        load_seg<VEC4, FULL>(rowp(1), pb, valid, b1);
+        load_seg<VEC4, FULL>(rowp(2), pb, valid, b2);
+        load_seg<VEC4, FULL>(rowp(3), pb, valid, b3);
     }
     // lane j holds the words of wave row k0 + j (64 rows of the period at a
     // time, read from the period's row table and broadcast with v_readlane)
@@ -329,7 +341,7 @@ __device__ __forceinline__ void wave_rows(const DenseArgs &a, uint32_t *qbins, u
         uint32_t C[DG];
 #pragma unroll
         for (int d = 0; d < DG; ++d) C[d] = process ? __builtin_amdgcn_readlane(CR[d], k - k0) : 0u;
-        scatter_row<DG, VEC4, FULL>(a, qaddr, buf, rowp(k + 4), scale, d0, lane, A2, S, valid, C, base, wsign,
+        scatter_row<DG, VEC4, FULL>(a, qaddr, buf, rowp(k + 4), scale, d0, pb, A2, S, valid, C, base, wsign,
                                     process);
     };
 
@@ -585,7 +597,8 @@ DenseLaunch plan_dense(const fcs_plan *p) {
     L.block_rows = fcs_ceil_div(rows, rb);
     L.row_blocks = fcs_ceil_div(rows, L.block_rows);
     const int64_t sb = std::max<int64_t>(1, std::min<int64_t>(nb / L.row_blocks, L.segs));
-    L.segs_per_block = std::min<int>((int)fcs_ceil_div(L.segs, sb), DS_WAVES);
+    // whole lane-order sets of GSEG segments per block
+    L.segs_per_block = std::min<int>((int)fcs_ceil_div(fcs_ceil_div(L.segs, sb), GSEG) * GSEG, DS_WAVES);
     L.seg_blocks = (int)fcs_ceil_div(L.segs, L.segs_per_block);
     L.blocks_per_slab = L.row_blocks;
     return L;
@@ -784,6 +797,147 @@ int coo_dg(const fcs_plan *p) {
 
 }  // namespace
 
+// Lane order of the dense kernel.  A wave issues each LDS atomic as two
+// half-waves (lanes 0-31, 32-63), and a half-wave takes as many passes as
+// the largest number of its lanes that hit one of the 32 LDS banks.  A lane
+// keeps its 4 consecutive columns (one 16-byte load), and in sketch d the
+// bank of column c is h_0(c) plus a row-uniform offset (mod 32), so the
+// assignment of column blocks to half-waves fixes the conflicts of every
+// row.  Within each set of GSEG segments (1024 columns, processed by GSEG
+// waves of one workgroup), the set's blocks may go to any half-wave of those
+// waves; any assignment is correct (each block is still loaded and added
+// exactly once per row), and a local search picks one with a small sum, over
+// the group's sketches and a block's 4 columns, of the largest bank load per
+// half-wave.  Entry (group, segment, lane) holds the lane's block index
+// within its set.
+size_t fcs_dense_perm_bytes(const fcs_plan *p) {
+    const int64_t I0 = p->I[0];
+    const int64_t segs = fcs_ceil_div(I0, SEG);
+    if ((double)I0 * (double)p->D > 16777216.0 || segs * p->D > 65536) return 0;
+    return (size_t)p->D * (size_t)segs * 64;
+}
+
+void fcs_dense_lane_order(const fcs_plan *p, const uint32_t *h0, uint8_t *perm) {
+    const int64_t I0 = p->I[0];
+    const int segs = (int)fcs_ceil_div(I0, SEG);
+    // identity: lane l of segment s loads block (s % GSEG) * 64 + l of its set
+    for (size_t k = 0; k < p->perm_bytes; ++k)
+        perm[k] = (uint8_t)((((k / 64) % (size_t)segs) % GSEG) * 64 + k % 64);
+    const DenseLaunch L = plan_dense(p);
+    if (L.dg == 0) return;
+    const int ngroups = (p->D + L.dg - 1) / L.dg;
+    const int nsets = (segs + GSEG - 1) / GSEG;
+    constexpr int MAX_SEARCHED = 16;     // (group, set) pairs searched; the rest keep the identity
+    constexpr int ITERS = 100000;
+    constexpr int NB = GSEG * 64;        // blocks of a full set
+    constexpr int NH = 2 * GSEG;         // half-waves of a full set
+    // per (half-wave, sketch-column pair): bank counts, how many banks hold
+    // each count, and the largest count (kept exactly under +-1 updates)
+    struct Hist {
+        int cnt[32];
+        int at[34];
+        int mx;
+    };
+    std::vector<int> bank((size_t)NB * 16);
+    std::vector<Hist> hist((size_t)NH * 16);
+    int searched = 0;
+    for (int gi = 0; gi < ngroups; ++gi) {
+        const int d0 = gi * L.dg;
+        const int nk = 4 * std::min(L.dg, p->D - d0);   // (sketch, column) pairs of a block
+        for (int st = 0; st < nsets && searched < MAX_SEARCHED; ++st, ++searched) {
+            const int ns = std::min(GSEG, segs - st * GSEG);   // segments (waves) in this set
+            const int nb = ns * 64, nh = 2 * ns;
+            if (nh < 2) continue;
+            for (int b = 0; b < nb; ++b)
+                for (int k = 0; k < nk; ++k) {
+                    const int64_t c = (int64_t)st * GSEG * SEG + 4 * b + (k & 3);
+                    bank[(size_t)b * 16 + k] = c < I0 ? (int)(h0[(size_t)(d0 + (k >> 2)) * I0 + c] & 31u) : -1;
+                }
+            std::vector<int> order(nb);
+            for (int b = 0; b < nb; ++b) order[b] = b;
+            for (int h = 0; h < nh; ++h)
+                for (int k = 0; k < nk; ++k) {
+                    Hist &t = hist[(size_t)h * 16 + k];
+                    std::fill(t.cnt, t.cnt + 32, 0);
+                    std::fill(t.at, t.at + 34, 0);
+                    t.at[0] = 32;
+                    t.mx = 0;
+                }
+            auto inc = [&](Hist &t, int b) {
+                const int v = t.cnt[b]++;
+                --t.at[v];
+                ++t.at[v + 1];
+                if (v + 1 > t.mx) t.mx = v + 1;
+            };
+            auto dec = [&](Hist &t, int b) {
+                const int v = t.cnt[b]--;
+                --t.at[v];
+                ++t.at[v - 1];
+                if (v == t.mx && t.at[v] == 0) t.mx = v - 1;
+            };
+            for (int b = 0; b < nb; ++b)
+                for (int k = 0; k < nk; ++k)
+                    if (bank[(size_t)b * 16 + k] >= 0) inc(hist[(size_t)(b >> 5) * 16 + k], bank[(size_t)b * 16 + k]);
+            uint64_t rs = p->seed ^ ((uint64_t)gi << 32) ^ (uint64_t)st;
+            for (int it = 0; it < ITERS; ++it) {
+                rs += 0x9E3779B97F4A7C15ull;
+                uint64_t z = rs;
+                z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+                z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+                z ^= z >> 31;
+                const int i = (int)(z % (uint64_t)nb), j = (int)((z >> 24) % (uint64_t)nb);
+                const int hi = i >> 5, hj = j >> 5;
+                if (hi == hj) continue;
+                const int bi = order[i], bj = order[j];
+                int delta = 0;
+                auto move = [&](int bfrom, int hfrom, int hto) {
+                    for (int k = 0; k < nk; ++k) {
+                        const int bk = bank[(size_t)bfrom * 16 + k];
+                        if (bk < 0) continue;
+                        Hist &a = hist[(size_t)hfrom * 16 + k], &c = hist[(size_t)hto * 16 + k];
+                        delta -= a.mx + c.mx;
+                        dec(a, bk);
+                        inc(c, bk);
+                        delta += a.mx + c.mx;
+                    }
+                };
+                move(bi, hi, hj);
+                move(bj, hj, hi);
+                if (delta <= 0) {
+                    order[i] = bj;
+                    order[j] = bi;
+                } else {
+                    move(bj, hi, hj);
+                    move(bi, hj, hi);
+                }
+            }
+            for (int ls = 0; ls < ns; ++ls)
+                for (int l = 0; l < 64; ++l)
+                    perm[((size_t)gi * segs + st * GSEG + ls) * 64 + l] = (uint8_t)order[ls * 64 + l];
+        }
+    }
+}
+
+// The lane order is searched on the host and uploaded on the plan's first
+// dense sketch (one synchronisation of that stream).  A call made while the
+// stream is being captured into a graph uses the identity order (same
+// result, more bank conflicts).  Returns whether the order is on the device.
+static bool dense_lane_order(fcs_plan *p, hipStream_t s) {
+    static std::mutex mu;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!p->perm_bytes || p->perm_ready) return p->perm_ready;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return false;
+    std::vector<uint32_t> h0((size_t)p->D * (size_t)p->I[0]);
+    fcs_mode0_hashes(p, h0.data());
+    std::vector<uint8_t> perm(p->perm_bytes);
+    fcs_dense_lane_order(p, h0.data(), perm.data());
+    if (hipMemcpyAsync((void *)p->perm, perm.data(), perm.size(), hipMemcpyHostToDevice, s) != hipSuccess) return false;
+    if (hipStreamSynchronize(s) != hipSuccess) return false;
+    p->perm_ready = true;
+    return true;
+}
+
 size_t fcs_ws_dense(const fcs_plan *) { return 256; }
 size_t fcs_ws_coo(const fcs_plan *) { return 256; }
 
@@ -831,6 +985,8 @@ extern "C" fcs_status fcs_sketch_dense(fcs_plan_t p, const float *T, float *out,
     a.seg_blocks = L.seg_blocks;
     a.segs_per_block = L.segs_per_block;
     a.period = (int)std::max<int64_t>(1, ADD_BOUND / std::max(1, p->m0));
+    a.dg_full = L.dg;
+    a.perm = dense_lane_order(p, s) ? p->perm : nullptr;
     const bool vec4 = (a.I0 % 4 == 0) && fcs_aligned(T, 16);
     const int full_groups = p->D / L.dg;
     const int tail = p->D - full_groups * L.dg;
