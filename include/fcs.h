@@ -119,6 +119,21 @@ FCS_API fcs_status fcs_plan_bind(fcs_plan_t plan, void *dev_tables, void *stream
 FCS_API fcs_status fcs_plan_export(fcs_plan_t plan, int32_t d, int32_t n,
                            int32_t *h_host, int8_t *s_host, void *stream);
 
+/* Lane order of the dense scatter (a performance detail of fcs_sketch_dense,
+ * exposed for inspection and tests; host computation, no device use, on a
+ * created plan, bound or not).  The dense kernel adds the sketches in groups
+ * of *group_size and streams rows of mode 0 in 256-column segments, one wave
+ * of 64 lanes per segment, each lane holding one 16-byte block (4 columns).
+ * For group g, segment s and lane l, out[(g * segs + s) * 64 + l] is the
+ * block that lane loads within the segment's set of 4 segments (1024
+ * columns), where segs = ceil(I_0 / 256); the blocks of a set are a
+ * permutation over its waves, chosen to spread the LDS banks of the
+ * group's bins.  fcs_plan_dense_order_bytes gives the size of `out` (0 when
+ * the plan keeps the plain order); group_size may be NULL.
+ * Errors: FCS_EINVAL (null plan or output, `bytes` too small). */
+FCS_API size_t fcs_plan_dense_order_bytes(fcs_plan_t plan);
+FCS_API fcs_status fcs_plan_dense_order(fcs_plan_t plan, uint8_t *out, size_t bytes, int32_t *group_size);
+
 /* Sizes of the plan: J~ (sketch length), L = Q * P (transform length), P
  * (FFT size) and Q (number of length-P slices of the transform).  Any output
  * pointer may be NULL. */

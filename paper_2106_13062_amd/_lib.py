@@ -47,6 +47,8 @@ SIGNATURES = {
     "fcs_plan_info": (I32, [P, ctypes.POINTER(I64), ctypes.POINTER(I64), ctypes.POINTER(I64),
                             ctypes.POINTER(I32)]),
     "fcs_plan_spec_len": (I64, [P]),
+    "fcs_plan_dense_order_bytes": (SZ, [P]),
+    "fcs_plan_dense_order": (I32, [P, P, SZ, ctypes.POINTER(I32)]),
     "fcs_plan_destroy": (I32, [P]),
     "fcs_workspace_bytes": (SZ, [P, I32, I64, I64]),
     "fcs_sketch_dense": (I32, [P, P, P, P, SZ, P]),

@@ -67,6 +67,8 @@ struct fcs_plan {
 // (h0[d * I_0 + i] = h_0 of sketch d); perm has perm_bytes entries
 size_t fcs_dense_perm_bytes(const fcs_plan *p);
 void fcs_dense_lane_order(const fcs_plan *p, const uint32_t *h0, uint8_t *perm);
+// sketches per group of the dense kernel's first pass (0: HBM fallback)
+int fcs_dense_group_size(const fcs_plan *p);
 // h_0 of every sketch on the host (plan.hip), h0[d * I_0 + i]
 void fcs_mode0_hashes(const fcs_plan *p, uint32_t *h0);
 

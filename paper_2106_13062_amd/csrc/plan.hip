@@ -372,6 +372,23 @@ extern "C" fcs_status fcs_plan_bind(fcs_plan_t p, void *dev_tables, void *stream
     return FCS_OK;
 }
 
+extern "C" size_t fcs_plan_dense_order_bytes(fcs_plan_t p) { return p ? p->perm_bytes : 0; }
+
+extern "C" fcs_status fcs_plan_dense_order(fcs_plan_t p, uint8_t *out, size_t bytes, int32_t *group_size) {
+    fcs_clear_error();
+    if (!p) FCS_FAIL(FCS_EINVAL, "null plan");
+    if (p->perm_bytes && !out) FCS_FAIL(FCS_EINVAL, "null output");
+    if (bytes < p->perm_bytes) FCS_FAIL(FCS_EINVAL, "output of %zu bytes, %zu needed", bytes, p->perm_bytes);
+    fcs_plan tmp = *p;           // the bind-time bound m0 on a copy
+    tmp.m0 = mode0_multiplicity(&tmp);
+    if (group_size) *group_size = fcs_dense_group_size(&tmp);
+    if (!p->perm_bytes) return FCS_OK;
+    std::vector<uint32_t> h0((size_t)p->D * (size_t)p->I[0]);
+    fcs_mode0_hashes(&tmp, h0.data());
+    fcs_dense_lane_order(&tmp, h0.data(), out);
+    return FCS_OK;
+}
+
 extern "C" fcs_status fcs_plan_export(fcs_plan_t p, int32_t d, int32_t n, int32_t *h_host,
                                       int8_t *s_host, void *stream) {
     fcs_clear_error();

@@ -810,6 +810,8 @@ int coo_dg(const fcs_plan *p) {
 // the group's sketches and a block's 4 columns, of the largest bank load per
 // half-wave.  Entry (group, segment, lane) holds the lane's block index
 // within its set.
+int fcs_dense_group_size(const fcs_plan *p) { return plan_dense(p).dg; }
+
 size_t fcs_dense_perm_bytes(const fcs_plan *p) {
     const int64_t I0 = p->I[0];
     const int64_t segs = fcs_ceil_div(I0, SEG);
