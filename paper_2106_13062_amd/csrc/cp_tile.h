@@ -241,19 +241,35 @@ template <int P>
 __device__ __forceinline__ void cp_tile(const CpDesc &c, int d, int q, int chunk, float2 *lds,
                                         float2 (&acc)[Shape<P>::E]) {
     constexpr int E = Shape<P>::E;
+    constexpr int T = Shape<P>::T;
     const int r0 = chunk * c.rchunk;
     const int r1 = min(c.R, r0 + c.rchunk);
 #pragma unroll
     for (int e = 0; e < E; ++e) acc[e] = make_float2(0.f, 0.f);
     const int32_t *invd = c.inv + (int64_t)d * c.iblock;
+    // a factor column that fits in the (not yet used) LDS of the transform is
+    // first copied there with coalesced loads, so the gather's random reads
+    // of it are LDS reads instead of scattered global loads
+    constexpr int LDS_FLOATS = 2 * Lds<P>::elems;
+    float *lu = reinterpret_cast<float *>(lds);
+    __syncthreads();
     for (int r = r0; r < r1; ++r) {
         float2 prod[E];
         const float lam = c.lambda ? c.lambda[r] : 1.0f;
         for (int n = 0; n < c.N; ++n) {
             const int32_t *off = invd + c.ioff[n];
+            const float *un = c.U[n] + (int64_t)r * c.I[n];
             float2 v[E];
-            build_cs_slice<P>(v, c.U[n] + (int64_t)r * c.I[n], off, off + c.J[n] + 1,
-                              off + c.J[n] + 1 + c.I[n], c.J[n], q, c.s, n == 0 ? lam : 1.0f);
+            if (c.I[n] <= LDS_FLOATS) {
+                for (int i = tid_opaque(); i < c.I[n]; i += T) lu[i] = un[i];
+                __syncthreads();
+                build_cs_slice<P>(v, lu, off, off + c.J[n] + 1, off + c.J[n] + 1 + c.I[n], c.J[n], q, c.s,
+                                  n == 0 ? lam : 1.0f);
+                __syncthreads();
+            } else {
+                build_cs_slice<P>(v, un, off, off + c.J[n] + 1, off + c.J[n] + 1 + c.I[n], c.J[n], q, c.s,
+                                  n == 0 ? lam : 1.0f);
+            }
             forward_regs<P>(lds, c.s.twP, v);
 #pragma unroll
             for (int e = 0; e < E; ++e) prod[e] = (n == 0) ? v[e] : cmul(prod[e], v[e]);
