@@ -156,9 +156,19 @@ __global__ __launch_bounds__(Shape<P>::T) void free_mode_kernel(FreeArgs a) {
         for (int n = 0; n < a.N; ++n) {
             if (n == f) continue;
             const int32_t *off = invd + a.ioff[n];
+            const float *vn = a.vecs[n] + (int64_t)p * a.I[n];
             float2 F[E];
-            build_cs_slice<P>(F, a.vecs[n] + (int64_t)p * a.I[n], off, off + a.J[n] + 1,
-                              off + a.J[n] + 1 + a.I[n], a.J[n], q, a.s, 1.0f);
+            if (a.I[n] <= 2 * Lds<P>::elems) {
+                // the vector fits in the transform's (free) LDS: stage it
+                // there so the gather reads LDS, as in the CP tiles
+                float *lv = reinterpret_cast<float *>(lds);
+                for (int i = tid_opaque(); i < a.I[n]; i += T) lv[i] = vn[i];
+                __syncthreads();
+                build_cs_slice<P>(F, lv, off, off + a.J[n] + 1, off + a.J[n] + 1 + a.I[n], a.J[n], q, a.s, 1.0f);
+                __syncthreads();
+            } else {
+                build_cs_slice<P>(F, vn, off, off + a.J[n] + 1, off + a.J[n] + 1 + a.I[n], a.J[n], q, a.s, 1.0f);
+            }
             forward_regs<P>(lds, a.s.twP, F);
 #pragma unroll
             for (int e = 0; e < E; ++e) X[e] = cmulc(X[e], F[e]);

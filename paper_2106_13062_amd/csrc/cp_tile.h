@@ -54,16 +54,18 @@ struct SliceArgs {
 // positions m = t + e*T of w_q, returned in registers w[e] (the inputs of
 // its first FFT pass).  u is the factor column (I_n floats); the inverse
 // lists give the buckets of h_n: `first` holds each bucket's first entry
-// (index, sign, more-entries flag), `off` / `ent` all entries in bucket
-// order.  A position costs two dependent loads (first-entry word, factor
-// value) unless its bucket holds several entries; the loads of G positions
-// are issued together so that their latencies overlap.
+// (index, sign, more-entries flag) and is followed by the J_n second-entry
+// words, `off` / `ent` all entries in bucket order.  A position costs two
+// independent entry-word loads and then its factor values, unless its
+// bucket holds three or more entries; the loads of G positions are issued
+// together so that their latencies overlap.
 template <int P>
 __device__ __forceinline__ float bucket_rest(const float *__restrict__ u, const int32_t *__restrict__ off,
                                              const int32_t *__restrict__ ent, int j) {
+    // entries from the third on (the first two come from the entry words)
     float y = 0.f;
     const int c1 = off[j + 1];
-    for (int k = off[j] + 1; k < c1; ++k) {
+    for (int k = off[j] + 2; k < c1; ++k) {
         const uint32_t w = (uint32_t)ent[k];
         y += __uint_as_float(__float_as_uint(u[w & FCS_H_MASK]) ^ (w & FCS_S_BIT));
     }
@@ -84,6 +86,7 @@ __device__ __forceinline__ void build_cs_slice(float2 (&wv)[Shape<P>::E], const 
     constexpr int T = Shape<P>::T;
     constexpr int E = Shape<P>::E;
     const int t = tid_opaque();
+    const int32_t *__restrict__ second = first + Jn;   // second-entry words follow the first ones
     if (Jn <= P) {
         // slice twist exp(-2 pi i q (t + eT) / L) = exp(-2 pi i q t / L) *
         // exp(-2 pi i q e T / L): one per-thread factor and E factors that
@@ -94,18 +97,19 @@ __device__ __forceinline__ void build_cs_slice(float2 (&wv)[Shape<P>::E], const 
         constexpr int G = (T >= 1024) ? E / 2 : E;
 #pragma unroll
         for (int g0 = 0; g0 < E; g0 += G) {
-            uint32_t f[G];
+            uint32_t f[G], f2[G];
 #pragma unroll
             for (int g = 0; g < G; ++g) {
                 const int j = t + (g0 + g) * T;
                 f[g] = (j < Jn) ? (uint32_t)first[j] : FCS_FIRST_EMPTY;
+                f2[g] = (j < Jn) ? (uint32_t)second[j] : FCS_FIRST_EMPTY;
             }
             float y[G];
 #pragma unroll
-            for (int g = 0; g < G; ++g) y[g] = bucket_first(u, f[g]);
+            for (int g = 0; g < G; ++g) y[g] = bucket_first(u, f[g]) + bucket_first(u, f2[g]);
 #pragma unroll
             for (int g = 0; g < G; ++g) {
-                if (f[g] != FCS_FIRST_EMPTY && (f[g] & FCS_MORE_BIT))
+                if (f2[g] != FCS_FIRST_EMPTY && (f2[g] & FCS_MORE_BIT))
                     y[g] += bucket_rest<P>(u, off, ent, t + (g0 + g) * T);
             }
 #pragma unroll
@@ -131,9 +135,9 @@ __device__ __forceinline__ void build_cs_slice(float2 (&wv)[Shape<P>::E], const 
         float2 acc = make_float2(0.f, 0.f);
         int qt = 0;
         for (int j = m; j < Jn; j += P) {
-            const uint32_t f = (uint32_t)first[j];
-            float y = bucket_first(u, f);
-            if (f != FCS_FIRST_EMPTY && (f & FCS_MORE_BIT)) y += bucket_rest<P>(u, off, ent, j);
+            const uint32_t f = (uint32_t)first[j], f2 = (uint32_t)second[j];
+            float y = bucket_first(u, f) + bucket_first(u, f2);
+            if (f2 != FCS_FIRST_EMPTY && (f2 & FCS_MORE_BIT)) y += bucket_rest<P>(u, off, ent, j);
             if (q == 0) {
                 acc.x += y;
             } else {

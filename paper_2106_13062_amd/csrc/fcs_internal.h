@@ -44,7 +44,8 @@ struct fcs_plan {
     // inverse hash lists (buckets of h_n), per sketch a block of iblock words:
     // for mode n at ioff[n]: J_n + 1 bucket offsets, then I_n entries
     // (index i | sign bit), entries of bucket j at [off[j], off[j+1]), then
-    // J_n first-entry words (FCS_IDX_MASK / FCS_MORE_BIT / FCS_FIRST_EMPTY)
+    // J_n first-entry words (FCS_IDX_MASK / FCS_MORE_BIT / FCS_FIRST_EMPTY),
+    // then J_n second-entry words (the same fields; MORE: a third entry)
     const int32_t *inv = nullptr;
     int64_t ioff[FCS_MAX_ORDER] = {0};
     int64_t iblock = 0;

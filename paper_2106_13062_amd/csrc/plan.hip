@@ -232,7 +232,7 @@ extern "C" fcs_status fcs_plan_create(const fcs_plan_desc *desc, fcs_plan_t *out
     tmp.iblock = 0;
     for (int n = 0; n < tmp.N; ++n) {
         tmp.ioff[n] = tmp.iblock;
-        tmp.iblock += tmp.J[n] + 1 + tmp.I[n] + tmp.J[n];
+        tmp.iblock += tmp.J[n] + 1 + tmp.I[n] + 2 * tmp.J[n];
     }
     tmp.inv_off = cur;
     cur = align256(cur + (size_t)tmp.D * (size_t)tmp.iblock * sizeof(int32_t));
@@ -276,17 +276,23 @@ static fcs_status build_inverse(const fcs_plan *p, int32_t *dev_inv, hipStream_t
                 const uint32_t h = w & FCS_H_MASK;
                 ent[fill[h]++] = (int32_t)((uint32_t)i | (w & FCS_S_BIT));
             }
-            // first-entry words (indices >= 2^30 are not gathered this way:
-            // the CP paths reject such modes)
+            // first- and second-entry words (indices >= 2^30 are not
+            // gathered this way: the CP paths reject such modes)
             int32_t *first = ent + In;
+            int32_t *second = first + Jn;
             for (int64_t j = 0; j < Jn; ++j) {
                 const int32_t c = off[j + 1] - off[j];
-                uint32_t f = FCS_FIRST_EMPTY;
+                uint32_t f = FCS_FIRST_EMPTY, g = FCS_FIRST_EMPTY;
                 if (c > 0) {
                     const uint32_t e = (uint32_t)ent[off[j]];
                     f = (e & FCS_IDX_MASK) | (e & FCS_S_BIT) | (c > 1 ? FCS_MORE_BIT : 0u);
                 }
+                if (c > 1) {
+                    const uint32_t e = (uint32_t)ent[off[j] + 1];
+                    g = (e & FCS_IDX_MASK) | (e & FCS_S_BIT) | (c > 2 ? FCS_MORE_BIT : 0u);
+                }
                 first[j] = (int32_t)f;
+                second[j] = (int32_t)g;
             }
         }
     }
