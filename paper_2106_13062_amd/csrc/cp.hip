@@ -162,7 +162,7 @@ __global__ __launch_bounds__(Shape<P>::T) void free_mode_kernel(FreeArgs a) {
                 // the vector fits in the transform's (free) LDS: stage it
                 // there so the gather reads LDS, as in the CP tiles
                 float *lv = reinterpret_cast<float *>(lds);
-                for (int i = tid_opaque(); i < a.I[n]; i += T) lv[i] = vn[i];
+                stage_column<T>(lv, vn, a.I[n]);
                 __syncthreads();
                 build_cs_slice<P>(F, lv, off, off + a.J[n] + 1, off + a.J[n] + 1 + a.I[n], a.J[n], q, a.s, 1.0f);
                 __syncthreads();

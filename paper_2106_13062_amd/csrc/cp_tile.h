@@ -211,6 +211,27 @@ struct InvTerms {
         return w.x * v.x + w.y * v.y;      // Re(conj(w) v)
     }
 };
+// Copy n floats from global memory to LDS with the workgroup's T threads:
+// 16 independent loads per thread are in flight before any is written, so a
+// column costs one memory latency per 16 T floats.
+template <int T>
+__device__ __forceinline__ void stage_column(float *dst, const float *__restrict__ src, int n) {
+    constexpr int CU = 16;
+    for (int i0 = tid_opaque(); i0 < n; i0 += T * CU) {
+        float v[CU];
+#pragma unroll
+        for (int k = 0; k < CU; ++k) {
+            const int i = i0 + k * T;
+            v[k] = i < n ? src[i] : 0.f;
+        }
+#pragma unroll
+        for (int k = 0; k < CU; ++k) {
+            const int i = i0 + k * T;
+            if (i < n) dst[i] = v[k];
+        }
+    }
+}
+
 // One CP (or Kronecker) sketch computation as the kernels see it.
 enum { FCS_DESC_CP = 0, FCS_DESC_KRON = 1 };
 
@@ -265,7 +286,7 @@ __device__ __forceinline__ void cp_tile(const CpDesc &c, int d, int q, int chunk
             const float *un = c.U[n] + (int64_t)r * c.I[n];
             float2 v[E];
             if (c.I[n] <= LDS_FLOATS) {
-                for (int i = tid_opaque(); i < c.I[n]; i += T) lu[i] = un[i];
+                stage_column<T>(lu, un, c.I[n]);
                 __syncthreads();
                 build_cs_slice<P>(v, lu, off, off + c.J[n] + 1, off + c.J[n] + 1 + c.I[n], c.J[n], q, c.s,
                                   n == 0 ? lam : 1.0f);
