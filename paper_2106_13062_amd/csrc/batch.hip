@@ -83,7 +83,8 @@ __device__ __forceinline__ void batch_tile(const BatchArgs &a, int t, float2 *ld
     const int nch = __builtin_amdgcn_readfirstlane(c.nchunks);
     const int Qh = __builtin_amdgcn_readfirstlane(c.s.Qh);
     float2 acc[Shape<P>::E];
-    cp_tile<P>(c, d, q, chunk, lds, acc);
+    // second-entry words on demand: persistent occupancy depends on registers
+    cp_tile<P, false>(c, d, q, chunk, lds, acc);
     if (nch == 1) {
         finish_slice<P>(c, d, q, lds, acc, slice_dst(c, d, q), false);
     } else {

@@ -77,7 +77,10 @@ __device__ __forceinline__ float bucket_first(const float *__restrict__ u, uint3
     return __uint_as_float(__float_as_uint(v) ^ (f & FCS_S_BIT));
 }
 
-template <int P>
+// EAGER2: load every position's second-entry word with its first one (one
+// latency for two-entry buckets, more registers); otherwise only for
+// buckets whose first word flags a second entry.
+template <int P, bool EAGER2 = true>
 __device__ __forceinline__ void build_cs_slice(float2 (&wv)[Shape<P>::E], const float *__restrict__ u,
                                                const int32_t *__restrict__ off,
                                                const int32_t *__restrict__ ent,
@@ -93,8 +96,9 @@ __device__ __forceinline__ void build_cs_slice(float2 (&wv)[Shape<P>::E], const 
         // are the same for every thread (q e T < Q P = L)
         const float2 wt = (q == 0) ? make_float2(1.f, 0.f) : s.twL[q * t];
         // positions t + e*T in groups of G (smaller groups for 1024-thread
-        // workgroups, whose register budget is half)
-        constexpr int G = (T >= 1024) ? E / 2 : E;
+        // workgroups, whose register budget is half, and for the persistent
+        // kernels, whose occupancy follows their register count)
+        constexpr int G = (T >= 1024 || (!EAGER2 && T >= 128)) ? E / 2 : E;
 #pragma unroll
         for (int g0 = 0; g0 < E; g0 += G) {
             uint32_t f[G], f2[G];
@@ -102,7 +106,15 @@ __device__ __forceinline__ void build_cs_slice(float2 (&wv)[Shape<P>::E], const 
             for (int g = 0; g < G; ++g) {
                 const int j = t + (g0 + g) * T;
                 f[g] = (j < Jn) ? (uint32_t)first[j] : FCS_FIRST_EMPTY;
-                f2[g] = (j < Jn) ? (uint32_t)second[j] : FCS_FIRST_EMPTY;
+                if (EAGER2) f2[g] = (j < Jn) ? (uint32_t)second[j] : FCS_FIRST_EMPTY;
+            }
+            if (!EAGER2) {
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    const int j = t + (g0 + g) * T;
+                    f2[g] = (f[g] != FCS_FIRST_EMPTY && (f[g] & FCS_MORE_BIT)) ? (uint32_t)second[j]
+                                                                             : FCS_FIRST_EMPTY;
+                }
             }
             float y[G];
 #pragma unroll
@@ -135,9 +147,15 @@ __device__ __forceinline__ void build_cs_slice(float2 (&wv)[Shape<P>::E], const 
         float2 acc = make_float2(0.f, 0.f);
         int qt = 0;
         for (int j = m; j < Jn; j += P) {
-            const uint32_t f = (uint32_t)first[j], f2 = (uint32_t)second[j];
-            float y = bucket_first(u, f) + bucket_first(u, f2);
-            if (f2 != FCS_FIRST_EMPTY && (f2 & FCS_MORE_BIT)) y += bucket_rest<P>(u, off, ent, j);
+            // the second-entry word only for buckets that have one (keeps
+            // the registers of this unrolled loop low)
+            const uint32_t f = (uint32_t)first[j];
+            float y = bucket_first(u, f);
+            if (f != FCS_FIRST_EMPTY && (f & FCS_MORE_BIT)) {
+                const uint32_t f2 = (uint32_t)second[j];
+                y += bucket_first(u, f2);
+                if (f2 & FCS_MORE_BIT) y += bucket_rest<P>(u, off, ent, j);
+            }
             if (q == 0) {
                 acc.x += y;
             } else {
@@ -262,7 +280,7 @@ struct CpDesc {
 
 // Forward tile (d, q, rank chunk): sum over the chunk's ranks of
 // lambda_r prod_n F_q(CS_n(U_n(:, r))); thread t returns X[t + e T] in acc.
-template <int P>
+template <int P, bool EAGER2 = true>
 __device__ __forceinline__ void cp_tile(const CpDesc &c, int d, int q, int chunk, float2 *lds,
                                         float2 (&acc)[Shape<P>::E]) {
     constexpr int E = Shape<P>::E;
@@ -288,11 +306,11 @@ __device__ __forceinline__ void cp_tile(const CpDesc &c, int d, int q, int chunk
             if (c.I[n] <= LDS_FLOATS) {
                 stage_column<T>(lu, un, c.I[n]);
                 __syncthreads();
-                build_cs_slice<P>(v, lu, off, off + c.J[n] + 1, off + c.J[n] + 1 + c.I[n], c.J[n], q, c.s,
+                build_cs_slice<P, EAGER2>(v, lu, off, off + c.J[n] + 1, off + c.J[n] + 1 + c.I[n], c.J[n], q, c.s,
                                   n == 0 ? lam : 1.0f);
                 __syncthreads();
             } else {
-                build_cs_slice<P>(v, un, off, off + c.J[n] + 1, off + c.J[n] + 1 + c.I[n], c.J[n], q, c.s,
+                build_cs_slice<P, EAGER2>(v, un, off, off + c.J[n] + 1, off + c.J[n] + 1 + c.I[n], c.J[n], q, c.s,
                                   n == 0 ? lam : 1.0f);
             }
             forward_regs<P>(lds, c.s.twP, v);
