@@ -62,12 +62,21 @@ struct SliceArgs {
 template <int P>
 __device__ __forceinline__ float bucket_rest(const float *__restrict__ u, const int32_t *__restrict__ off,
                                              const int32_t *__restrict__ ent, int j) {
-    // entries from the third on (the first two come from the entry words)
+    // entries from the third on (the first two come from the entry words):
+    // the loads of up to four of them are issued together, a loop takes any
+    // further ones
+    constexpr int K = 4;
+    const int k0 = off[j] + 2, c1 = off[j + 1];
+    uint32_t w[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i) w[i] = (k0 + i < c1) ? (uint32_t)ent[k0 + i] : 0u;
     float y = 0.f;
-    const int c1 = off[j + 1];
-    for (int k = off[j] + 2; k < c1; ++k) {
-        const uint32_t w = (uint32_t)ent[k];
-        y += __uint_as_float(__float_as_uint(u[w & FCS_H_MASK]) ^ (w & FCS_S_BIT));
+#pragma unroll
+    for (int i = 0; i < K; ++i)
+        if (k0 + i < c1) y += __uint_as_float(__float_as_uint(u[w[i] & FCS_H_MASK]) ^ (w[i] & FCS_S_BIT));
+    for (int k = k0 + K; k < c1; ++k) {
+        const uint32_t v = (uint32_t)ent[k];
+        y += __uint_as_float(__float_as_uint(u[v & FCS_H_MASK]) ^ (v & FCS_S_BIT));
     }
     return y;
 }
