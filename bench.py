@@ -399,6 +399,52 @@ def serve_requests(srv, args, rate, count, seed):
     return reqs
 
 
+def rtpm_workload(args, torch, dev):
+    """Sketched robust tensor power method (Section 5, RTPM) in the setting of
+    the paper's synthetic experiment: a symmetric 100^3 tensor of CP rank 10
+    (orthonormal basis, unit weights) plus Gaussian noise at level 0.01 (read
+    as ||N|| = 0.01 ||T||), D = 2 sketches, 15 starts, 20 power iterations,
+    J_n = 5000.  Timed: the dense
+    sketch of the tensor plus the whole decomposition (host syncs for the
+    choice of start included).  Quality: residual ||T - sum lam u o u o u|| /
+    ||T|| and the overlap of each component with the planted basis."""
+    import synth
+    from paper_2106_13062_amd import Plan
+    from paper_2106_13062_amd.rtpm import rtpm
+    I, R, D, L, iters, J, sigma = 100, 10, 2, 15, 20, 5000, 0.01
+    # noise level sigma read relative to the tensor: ||N|| = sigma ||T_clean||
+    # (per-entry std sigma * ||T_clean|| / sqrt(I^3); ||T_clean|| = sqrt(R))
+    Tv, A = synth.symmetric_cp_tensor(synth.DATA_SEED["rtpm100"], I, np.ones(R), sigma * np.sqrt(R) / I ** 1.5)
+    starts = torch.from_numpy(synth.rtpm_starts(synth.DATA_SEED["rtpm100"], R, L, I, stream=7)).to(dev)
+    plan = Plan((I, I, I), (J, J, J), D, synth.HASH_SEED["rtpm100"], device=dev)
+    T = torch.from_numpy(Tv.astype(np.float32)).to(dev)
+
+    def run():
+        y = plan.sketch_dense(T)
+        return rtpm(plan, y, starts, iters)
+
+    run()
+    torch.cuda.synchronize()
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        lam, U = run()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    Ud = U.double()
+    approx = torch.einsum("r,ir,jr,kr->kji", lam.to(dev), Ud.T, Ud.T, Ud.T).reshape(-1)
+    Td = T.double()
+    resid = (torch.linalg.vector_norm(Td - approx) / torch.linalg.vector_norm(Td)).item()
+    clean = torch.from_numpy(synth.symmetric_cp_tensor(synth.DATA_SEED["rtpm100"], I, np.ones(R))[0]).to(dev)
+    resid_clean = (torch.linalg.vector_norm(clean - approx) / torch.linalg.vector_norm(clean)).item()
+    overlap = np.abs(U.double().cpu().numpy() @ A).max(axis=1)
+    return {"workload": "rtpm100: symmetric 100^3 CP rank 10 (orthonormal basis, unit weights) + Gaussian noise of "
+                        "norm 0.01 ||T||, D=2, 15 starts, 20 iterations, J_n=5000", "ms": ms, "residual": resid,
+            "noise_floor": sigma * np.sqrt(R) / float(Td.norm()),
+            "residual_vs_clean": resid_clean, "min_overlap": float(overlap.min()),
+            "eigenvalues": [round(float(x), 5) for x in lam]}
+
+
 def serve_workload(args, torch, dev):
     """Poisson request streams at several rates through the continuous
     batching server, against the same requests served one at a time."""
@@ -476,7 +522,7 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=1 << 19,
                     help="rows of the tensor the CPU oracle sketches")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "dense1024_traffic.json"))
-    ap.add_argument("--mode", default="full", choices=["full", "dense", "cp", "batch", "serve", "copy"],
+    ap.add_argument("--mode", default="full", choices=["full", "dense", "cp", "batch", "serve", "rtpm", "copy"],
                     help="full: headline + secondary workloads; dense: headline only; cp: the CP "
                          "sketches and T(I,u,v) only; batch: the uneven batch only; serve: the "
                          "serving loop only; copy: plain copy kernel for counter calibration")
@@ -510,6 +556,9 @@ def main():
     if args.mode == "serve":
         print(json.dumps({"serve": serve_workload(args, torch, dev)}), flush=True)
         return
+    if args.mode == "rtpm":
+        print(json.dumps({"rtpm": rtpm_workload(args, torch, dev)}), flush=True)
+        return
     if args.mode == "cp":
         import synth
         print(json.dumps({"cp100": cp_workload(args, torch, dev, synth.CP100),
@@ -533,6 +582,8 @@ def main():
         torch.cuda.empty_cache()
         log("secondary: serving loop")
         secondary["serve"] = serve_workload(args, torch, dev)
+        log("secondary: sketched RTPM")
+        secondary["rtpm"] = rtpm_workload(args, torch, dev)
     del T
     # HBM traffic per launch from the committed FETCH_SIZE / WRITE_SIZE
     # summary, only while the kernel source is the one that was measured

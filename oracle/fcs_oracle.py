@@ -42,6 +42,9 @@ Parity status of each function (what pins it is in ``tests/test_oracle_*.py``):
                           brute-force sketch of e_i o u o v (Section 4.1).
 * ``kron_fcs``           pinned against ``fcs_dense`` of the materialised
                           order-4 tensor (Section 4.3).
+* ``rtpm``               pinned by recovering the planted components and
+                          weights of an orthogonally decomposable symmetric
+                          tensor (the setting of the RTPM experiments).
 """
 from __future__ import annotations
 
@@ -357,3 +360,45 @@ def kron_decompress(y, h, s, I) -> np.ndarray:
     paper's modulo never wraps)."""
     H, S = _bins_and_signs(h, s, tuple(int(i) for i in I))
     return S * np.asarray(y, dtype=np.float64)[H]
+
+
+# ---------------------------------------------------------------------------
+# Robust tensor power method on sketches (Section 5: RTPM for a symmetric
+# order-3 tensor, with T(I,u,u) and T(u,u,u) estimated from D sketches as in
+# Section 4.1).  For each component: power iterations u <- T(I,u,u) /
+# ||T(I,u,u)|| from several starting vectors, the eigenvalue T(u,u,u) of
+# each, the start with the largest eigenvalue kept, then deflation of the
+# sketches by linearity: FCS(T - lam u o u o u) = FCS(T) - lam FCS(u o u o u).
+# ---------------------------------------------------------------------------
+def fcs_rank1(vecs, h, s, J) -> np.ndarray:
+    """FCS of the rank-1 tensor v_0 o ... o v_{N-1}: the linear convolution
+    of the mode count sketches (Section 3.1)."""
+    g = np.ones(1)
+    for n, v in enumerate(vecs):
+        g = np.convolve(g, count_sketch(v, h[n], s[n], int(J[n])))
+    return g
+
+
+def rtpm(Y, hs, ss, J, rank: int, inits, iters: int):
+    """Y: D x J~ sketches of a symmetric I x I x I tensor (sketch d with hash
+    pairs hs[d], ss[d]); inits: rank x L x I starting vectors (the random
+    draws are inputs).  Returns (eigenvalues [rank], components rank x I)."""
+    Y = np.array(Y, dtype=np.float64)          # deflated in place
+    D = Y.shape[0]
+    lams, comps = [], []
+    for k in range(rank):
+        U = np.array(inits[k], dtype=np.float64)
+        U = U / np.linalg.norm(U, axis=1, keepdims=True)
+        for _ in range(iters):
+            W = np.stack([contract_free_median(Y, hs, ss, J, 0, [u, u]) for u in U])
+            U = W / np.linalg.norm(W, axis=1, keepdims=True)
+        lam = np.array([median([contract_full(Y[d], hs[d], ss[d], J, [u, u, u]) for d in range(D)])
+                        for u in U])
+        j = int(np.argmax(lam))
+        u = U[j]
+        lams.append(float(lam[j]))
+        comps.append(u)
+        for d in range(D):
+            Y[d] -= lam[j] * fcs_rank1([u, u, u], hs[d], ss[d], J)
+    return np.array(lams), np.stack(comps)
+

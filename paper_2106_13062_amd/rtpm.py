@@ -1,0 +1,65 @@
+"""Robust tensor power method on fast count sketches (Section 5 of the
+paper: RTPM for a symmetric order-3 tensor, with the contractions of
+Section 4.1 estimated from D sketches).
+
+For each component k:
+  * power iterations u <- T(I,u,u) / ||T(I,u,u)|| from ``L`` starting
+    vectors at once: T(I,u,u) is the free-mode contraction of the sketch
+    spectra (fcs_contract_free_mode, median over the D sketches);
+  * the eigenvalue T(u,u,u) of every start: the median over d of
+    <FCS_d(T), FCS_d(u o u o u)> (fcs_sketch_cp of the rank-1 tensor, then
+    fcs_contract_inner);
+  * the start with the largest eigenvalue is kept, and the sketch and its
+    spectra are deflated by linearity:
+    FCS(T - lam u o u o u) = FCS(T) - lam FCS(u o u o u).
+
+The starting vectors are inputs (the random draws of the method).  Vector
+normalisation, the argmax over starts and the subtraction of the deflation
+term are small elementwise steps done with torch on the device; every
+sketch and contraction runs in the library's kernels.
+"""
+from __future__ import annotations
+
+import torch
+
+from .fcs import Plan
+
+
+def rtpm(plan: Plan, y: torch.Tensor, starts: torch.Tensor, iters: int, stream=None):
+    """plan: bound Plan of shape (I, I, I); y: float32 D x J~ sketch of the
+    tensor (not modified); starts: float32 rank x L x I starting vectors.
+    Returns (eigenvalues float64 [rank] on the host, components float32
+    rank x I on the device)."""
+    if plan.N != 3 or not (plan.I[0] == plan.I[1] == plan.I[2]):
+        raise ValueError("RTPM needs a plan of a cubic order-3 shape")
+    rank, L, I = (int(x) for x in starts.shape)
+    if I != plan.I[0]:
+        raise ValueError("starting vectors must have I entries")
+    s = torch.cuda.current_stream() if stream is None else stream
+    with torch.cuda.stream(s):
+        y = y.clone()
+        spec = plan.spectrum(y, stream=s)
+        lams = []
+        comps = torch.empty((rank, I), dtype=torch.float32, device=y.device)
+        for k in range(rank):
+            U = starts[k].to(torch.float32)
+            U = (U / torch.linalg.vector_norm(U, dim=1, keepdim=True)).contiguous()
+            for _ in range(iters):
+                W = plan.contract_free_mode(spec, 0, [None, U, U], stream=s)
+                U = (W / torch.linalg.vector_norm(W, dim=1, keepdim=True)).to(torch.float32).contiguous()
+            lam = torch.empty(L, dtype=torch.float64, device=y.device)
+            for j in range(L):
+                uj = U[j:j + 1]
+                yj, _ = plan.sketch_cp([uj, uj, uj], stream=s)
+                med, _ = plan.contract_inner(y, yj, stream=s)
+                lam[j:j + 1] = med
+            j = int(torch.argmax(lam).item())
+            lk = float(lam[j].item())
+            u = U[j:j + 1].contiguous()
+            lams.append(lk)
+            comps[k] = u[0]
+            lt = torch.tensor([lk], dtype=torch.float32, device=y.device)
+            yk, sk = plan.sketch_cp([u, u, u], lam=lt, want_spec=True, stream=s)
+            y -= yk
+            spec -= sk
+    return torch.tensor(lams, dtype=torch.float64), comps

@@ -32,9 +32,9 @@ CHUNK = 1 << 22          # entries per independently seeded chunk
 _WORKERS = max(1, min(16, os.cpu_count() or 1))
 
 DATA_SEED = {"cp100": 1001, "dense1024": 1002, "cp10k": 1003, "batch4096": 1004,
-             "serve": 1005}
+             "serve": 1005, "rtpm100": 1006}
 HASH_SEED = {"cp100": 2001, "dense1024": 2002, "cp10k": 2003, "batch4096": 2004,
-             "serve": 2005}
+             "serve": 2005, "rtpm100": 2006}
 
 
 def rng(seed: int, *stream: int) -> np.random.Generator:
@@ -128,6 +128,33 @@ def unit_vectors(seed: int, count: int, size: int, stream: int = 0) -> np.ndarra
 
 def uniform_matrix(seed: int, shape, lo=-5.0, hi=5.0, stream: int = 0):
     return rng(seed, stream).uniform(lo, hi, size=shape).astype(np.float32)
+
+
+def orthonormal_columns(seed: int, size: int, count: int, stream: int = 0) -> np.ndarray:
+    """``size`` x ``count`` float64 matrix with orthonormal columns: the Q
+    factor of a Gaussian draw, signs fixed by R's diagonal (a random
+    orthonormal basis)."""
+    q, r = np.linalg.qr(rng(seed, stream).standard_normal((int(size), int(count))))
+    return q * np.sign(np.diag(r))
+
+
+def symmetric_cp_tensor(seed: int, size: int, weights, noise: float = 0.0, stream: int = 0):
+    """The order-3 tensor sum_r w_r a_r o a_r o a_r of the RTPM experiments
+    (a_r orthonormal columns of ``orthonormal_columns``) plus i.i.d.
+    N(0, noise^2) entries.  Returns (vec(T) float64 with mode 0 fastest,
+    A = [a_0 .. a_{R-1}] size x R)."""
+    w = np.asarray(weights, dtype=np.float64)
+    A = orthonormal_columns(seed, size, len(w), stream)
+    T = np.einsum("r,ir,jr,kr->ijk", w, A, A, A)
+    if noise:
+        T = T + noise * rng(seed, stream + 1).standard_normal(T.shape)
+    return T.reshape(-1, order="F"), A
+
+
+def rtpm_starts(seed: int, rank: int, count: int, size: int, stream: int = 0) -> np.ndarray:
+    """rank x count x size float32 unit starting vectors of the power
+    iterations (one set per component)."""
+    return unit_vectors(seed, rank * count, size, stream).reshape(int(rank), int(count), int(size))
 
 
 # ----------------------------------------------------------------------------
