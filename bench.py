@@ -445,6 +445,50 @@ def rtpm_workload(args, torch, dev):
             "eigenvalues": [round(float(x), 5) for x in lam]}
 
 
+def als_workload(args, torch, dev):
+    """Sketched alternating least squares (Section 5, ALS) in the setting of
+    the paper's synthetic experiment: an asymmetric 400^3 tensor of CP rank
+    10 (three independent orthonormal factors, unit weights) plus Gaussian
+    noise at level 0.01 (read as ||N|| = 0.01 ||T||), D = 10 sketches,
+    J_n = 5000, 20 iterations from N(0, 1) starting factors.  Timed: the dense
+    sketch of the tensor plus the whole decomposition.  Quality: residual
+    ||T - sum lam a o b o c|| / ||T|| and the overlap of each recovered
+    column with the planted factors."""
+    import synth
+    from paper_2106_13062_amd import Plan
+    from paper_2106_13062_amd.als import als
+    I, R, D, iters, J, sigma = 400, 10, 10, 20, 5000, 0.01
+    Tv, F = synth.asymmetric_cp_tensor(synth.DATA_SEED["als400"], I, np.ones(R), sigma * np.sqrt(R) / I ** 1.5)
+    T = torch.from_numpy(Tv.astype(np.float32)).to(dev)
+    del Tv
+    init = [torch.from_numpy(f).to(dev) for f in synth.als_init(synth.DATA_SEED["als400"], I, R, stream=9)]
+    plan = Plan((I, I, I), (J, J, J), D, synth.HASH_SEED["als400"], device=dev)
+
+    def run():
+        y = plan.sketch_dense(T)
+        return als(plan, y, init, iters)
+
+    run()
+    torch.cuda.synchronize()
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        lam, G = run()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    Gd = [g.double() for g in G]
+    approx = torch.einsum("r,ir,jr,kr->kji", lam, *Gd).reshape(-1)
+    Td = T.double()
+    resid = (torch.linalg.vector_norm(Td - approx) / torch.linalg.vector_norm(Td)).item()
+    del approx, Td
+    overlap = min(float(np.abs(Gd[n].cpu().numpy().T @ F[n]).max(axis=1).min()) for n in range(3))
+    plan.close()
+    return {"workload": "als400: asymmetric 400^3 CP rank 10 (orthonormal factors, unit weights) + Gaussian noise "
+                        "of norm 0.01 ||T||, D=10, J_n=5000, 20 iterations", "ms": ms, "residual": resid,
+            "noise_floor": sigma, "min_overlap": overlap,
+            "weights": [round(float(x), 5) for x in lam.cpu()]}
+
+
 def serve_workload(args, torch, dev):
     """Poisson request streams at several rates through the continuous
     batching server, against the same requests served one at a time."""
@@ -522,7 +566,7 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=1 << 19,
                     help="rows of the tensor the CPU oracle sketches")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "dense1024_traffic.json"))
-    ap.add_argument("--mode", default="full", choices=["full", "dense", "cp", "batch", "serve", "rtpm", "copy"],
+    ap.add_argument("--mode", default="full", choices=["full", "dense", "cp", "batch", "serve", "rtpm", "als", "copy"],
                     help="full: headline + secondary workloads; dense: headline only; cp: the CP "
                          "sketches and T(I,u,v) only; batch: the uneven batch only; serve: the "
                          "serving loop only; copy: plain copy kernel for counter calibration")
@@ -559,6 +603,9 @@ def main():
     if args.mode == "rtpm":
         print(json.dumps({"rtpm": rtpm_workload(args, torch, dev)}), flush=True)
         return
+    if args.mode == "als":
+        print(json.dumps({"als": als_workload(args, torch, dev)}), flush=True)
+        return
     if args.mode == "cp":
         import synth
         print(json.dumps({"cp100": cp_workload(args, torch, dev, synth.CP100),
@@ -584,6 +631,8 @@ def main():
         secondary["serve"] = serve_workload(args, torch, dev)
         log("secondary: sketched RTPM")
         secondary["rtpm"] = rtpm_workload(args, torch, dev)
+        log("secondary: sketched ALS")
+        secondary["als"] = als_workload(args, torch, dev)
     del T
     # HBM traffic per launch from the committed FETCH_SIZE / WRITE_SIZE
     # summary, only while the kernel source is the one that was measured

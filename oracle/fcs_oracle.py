@@ -45,6 +45,11 @@ Parity status of each function (what pins it is in ``tests/test_oracle_*.py``):
 * ``rtpm``               pinned by recovering the planted components and
                           weights of an orthogonally decomposable symmetric
                           tensor (the setting of the RTPM experiments).
+* ``als``                pinned by recovering the planted factors and
+                          weights of an asymmetric tensor with orthonormal
+                          factors (the setting of the ALS experiment), and by
+                          the plain ALS step it reduces to when the
+                          contractions are exact.
 """
 from __future__ import annotations
 
@@ -402,3 +407,42 @@ def rtpm(Y, hs, ss, J, rank: int, inits, iters: int):
             Y[d] -= lam[j] * fcs_rank1([u, u, u], hs[d], ss[d], J)
     return np.array(lams), np.stack(comps)
 
+
+
+# ---------------------------------------------------------------------------
+# Alternating least squares on sketches (Section 5, ALS for an order-3
+# tensor).  Mode n is updated from the product of the mode-n unfolding with
+# the Khatri-Rao product of the other factors; column r of that product is
+# the contraction of T with the r-th columns of the other factors at their
+# own modes and the identity at mode n (estimated from the D sketches as in
+# Section 4.1).  Then, as in plain ALS, the factor is that matrix times the
+# inverse of the Hadamard product of the other factors' Gram matrices, and
+# its columns are normalised into the weights.
+# ---------------------------------------------------------------------------
+def als_step(M, others):
+    """Plain ALS update of one mode: M (I_n x R) is the mode's
+    unfolding-times-Khatri-Rao product, ``others`` the other factor matrices.
+    Returns (weights [R], unit-column factor I_n x R)."""
+    R = M.shape[1]
+    G = np.ones((R, R))
+    for F in others:
+        G = G * (F.T @ F)
+    U = np.linalg.solve(G, np.asarray(M, dtype=np.float64).T).T
+    lam = np.linalg.norm(U, axis=0)
+    return lam, U / lam
+
+
+def als(Y, hs, ss, J, init, iters: int):
+    """Y: D x J~ sketches of an order-3 tensor; init: three starting factor
+    matrices (I_n x R, the random draws are inputs).  Each iteration updates
+    modes 0, 1, 2 in turn.  Returns (weights [R], [A_0, A_1, A_2])."""
+    F = [np.array(f, dtype=np.float64) for f in init]
+    R = F[0].shape[1]
+    lam = np.ones(R)
+    for _ in range(iters):
+        for n in range(3):
+            o = [m for m in range(3) if m != n]
+            M = np.stack([contract_free_median(Y, hs, ss, J, n, [F[m][:, r] for m in o])
+                          for r in range(R)], axis=1)
+            lam, F[n] = als_step(M, [F[m] for m in o])
+    return lam, F

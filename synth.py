@@ -32,9 +32,11 @@ CHUNK = 1 << 22          # entries per independently seeded chunk
 _WORKERS = max(1, min(16, os.cpu_count() or 1))
 
 DATA_SEED = {"cp100": 1001, "dense1024": 1002, "cp10k": 1003, "batch4096": 1004,
-             "serve": 1005, "rtpm100": 1006}
+             "serve": 1005, "rtpm100": 1006,
+             "als400": 1007}
 HASH_SEED = {"cp100": 2001, "dense1024": 2002, "cp10k": 2003, "batch4096": 2004,
-             "serve": 2005, "rtpm100": 2006}
+             "serve": 2005, "rtpm100": 2006,
+             "als400": 2007}
 
 
 def rng(seed: int, *stream: int) -> np.random.Generator:
@@ -149,6 +151,25 @@ def symmetric_cp_tensor(seed: int, size: int, weights, noise: float = 0.0, strea
     if noise:
         T = T + noise * rng(seed, stream + 1).standard_normal(T.shape)
     return T.reshape(-1, order="F"), A
+
+
+def asymmetric_cp_tensor(seed: int, size: int, weights, noise: float = 0.0, stream: int = 0):
+    """The order-3 tensor sum_r w_r a_r o b_r o c_r of the ALS experiment
+    (each factor a set of orthonormal columns, drawn independently) plus
+    i.i.d. N(0, noise^2) entries.  Returns (vec(T) float64 with mode 0
+    fastest, [A, B, C])."""
+    w = np.asarray(weights, dtype=np.float64)
+    F = [orthonormal_columns(seed, size, len(w), stream + 3 * k) for k in range(3)]
+    T = np.einsum("r,ir,jr,kr->ijk", w, *F)
+    if noise:
+        T = T + noise * rng(seed, stream + 1).standard_normal(T.shape)
+    return T.reshape(-1, order="F"), F
+
+
+def als_init(seed: int, size: int, rank: int, stream: int = 0):
+    """Three float32 size x rank starting factors of ALS, N(0, 1) entries."""
+    g = rng(seed, stream)
+    return [g.standard_normal((int(size), int(rank))).astype(np.float32) for _ in range(3)]
 
 
 def rtpm_starts(seed: int, rank: int, count: int, size: int, stream: int = 0) -> np.ndarray:

@@ -1,0 +1,52 @@
+"""Sketched alternating least squares on the GPU (Section 5, ALS) against the
+FP64 oracle run on the same inputs: same tensor, same hash tables (the
+plan's), same starting factors.  Every weight agrees to 1e-4 relative and
+every factor column to 1 - |cos| <= 1e-4; both recover the planted
+factors."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synth
+from paper_2106_13062_amd import Plan
+from paper_2106_13062_amd.als import als
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+@pytest.mark.parametrize("I,J,D,w,noise,iters,tseed,hseed,iseed", [
+    (16, 4096, 3, (3.0, 2.0, 1.0), 0.0, 15, 12, 22, 32),
+    (20, 4096, 3, (2.0, 1.0), 0.01, 12, 13, 23, 33),
+])
+def test_als_matches_oracle(I, J, D, w, noise, iters, tseed, hseed, iseed):
+    print(f"als I={I} J={J} D={D} R={len(w)}", flush=True)
+    R = len(w)
+    Tv, F = synth.asymmetric_cp_tensor(tseed, I, w, noise)
+    init = synth.als_init(iseed, I, R)
+    plan = Plan((I, I, I), (J, J, J), D, hseed, device=DEV)
+    y = plan.sketch_dense(torch.from_numpy(Tv.astype(np.float32)).to(DEV))
+    lam_g, G_g = als(plan, y, [torch.from_numpy(f).to(DEV) for f in init], iters)
+    torch.cuda.synchronize()
+    lam_g = lam_g.cpu().numpy()
+    G_g = [g.cpu().numpy().astype(np.float64) for g in G_g]
+    hs, ss = O.hash_tables(hseed, D, (I, I, I), (J, J, J))
+    T = Tv.astype(np.float32).astype(np.float64).reshape((I, I, I), order="F")
+    Y = np.stack([O.fcs_dense(T, hs[d], ss[d], (J, J, J)) for d in range(D)])
+    lam_o, G_o = O.als(Y, hs, ss, (J, J, J), init, iters)
+    assert np.all(np.abs(lam_g - lam_o) <= 1e-4 * np.abs(lam_o)), (lam_g, lam_o)
+    for n in range(3):
+        cos = np.abs(np.sum(G_g[n] * G_o[n], axis=0)) / np.linalg.norm(G_g[n], axis=0)
+        assert np.all(1.0 - cos <= 1e-4), (n, cos)
+        assert np.all(np.abs(G_g[n].T @ F[n]).max(axis=1) >= 0.99)
+
+
+def test_als_rejects_bad_shapes():
+    plan = Plan((8, 8, 8), (64, 64, 64), 2, 1, device=DEV)
+    y = plan.sketch_dense(torch.zeros(512, device=DEV))
+    with pytest.raises(ValueError):
+        als(plan, y, [torch.zeros((8, 2), device=DEV)] * 2, 1)
+    with pytest.raises(ValueError):
+        als(plan, y, [torch.zeros((8, 2), device=DEV), torch.zeros((7, 2), device=DEV),
+                      torch.zeros((8, 2), device=DEV)], 1)
