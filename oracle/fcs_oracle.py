@@ -42,6 +42,12 @@ Parity status of each function (what pins it is in ``tests/test_oracle_*.py``):
                           brute-force sketch of e_i o u o v (Section 4.1).
 * ``kron_fcs``           pinned against ``fcs_dense`` of the materialised
                           order-4 tensor (Section 4.3).
+* ``contraction_fcs``    pinned against ``fcs_dense`` of the materialised
+                          contraction (Section 4.3).
+* ``decompress_median``  pinned by the paper's 1-based decompression rule
+                          written as explicit loops, by the order-statistic
+                          median, by exact recovery of a lone entry and by
+                          near-exact recovery at long hash lengths.
 * ``rtpm``               pinned by recovering the planted components and
                           weights of an orthogonally decomposable symmetric
                           tensor (the setting of the RTPM experiments).
@@ -357,6 +363,24 @@ def kron_fcs(A, B, h, s, J) -> np.ndarray:
     b = fcs_dense(B, h[2:4], s[2:4], J[2:4])
     Jt = sketch_length(J)
     return np.fft.ifft(np.fft.fft(a, n=Jt) * np.fft.fft(b, n=Jt)).real.copy()
+
+
+def contraction_fcs(A, B, h, s, J) -> np.ndarray:
+    """FCS of the contraction C[i1,i2,i3,i4] = sum_l A[i1,i2,l] B[l,i3,i4]
+    (Section 4.3): the sum over l of the Kronecker-product sketches of the
+    slices A(:,:,l) and B(l,:,:)."""
+    A = np.asarray(A, dtype=np.float64)
+    B = np.asarray(B, dtype=np.float64)
+    return sum(kron_fcs(A[:, :, l], B[l], h, s, J) for l in range(A.shape[2]))
+
+
+def decompress_median(Y, hs, ss, I) -> np.ndarray:
+    """The tensor recovered from D sketches Y (D x J~): per sketch, entry i
+    is S(i) FCS[H(i)] (the decompression rule of Section 4.3, for any
+    order), and the D estimates are reduced by the median (Section 5: the
+    median over independent sketches)."""
+    est = np.stack([kron_decompress(Y[d], hs[d], ss[d], I) for d in range(len(Y))])
+    return median(est, axis=0)
 
 
 def kron_decompress(y, h, s, I) -> np.ndarray:
