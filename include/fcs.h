@@ -159,11 +159,12 @@ enum {
     FCS_OP_INNER = 3,        /* fcs_contract_inner                          */
     FCS_OP_FREE_MODE = 4,    /* fcs_contract_free_mode with P pairs         */
     FCS_OP_SPECTRUM = 5,     /* fcs_sketch_spectrum                         */
-    FCS_OP_KRON = 6          /* fcs_sketch_kron                             */
+    FCS_OP_KRON = 6,         /* fcs_sketch_kron                             */
+    FCS_OP_CONTRACTION = 7   /* fcs_sketch_contraction, R = shared length   */
 };
 
-/* Device workspace bytes an operation needs (R: CP rank, P: vector pairs;
- * ignored where irrelevant).  Returns 0 for an invalid operation. */
+/* Device workspace bytes an operation needs (R: CP rank, or the shared index
+ * length of a contraction; P: vector pairs; ignored where irrelevant).  Returns 0 for an invalid operation. */
 FCS_API size_t fcs_workspace_bytes(fcs_plan_t plan, int32_t op, int64_t R, int64_t P);
 
 /* Dense sketch, general-tensor formula of Section 3.2, all D sketches in one
@@ -224,6 +225,49 @@ FCS_API fcs_status fcs_sketch_cp(fcs_plan_t plan, int64_t R, const float *const 
 FCS_API fcs_status fcs_sketch_kron(fcs_plan_t plan, const float *A, const float *B,
                            float *out, float *spec, void *ws, size_t ws_bytes,
                            void *stream);
+
+/* Tensor contraction compression, Section 4.3: the FCS of
+ * C[i0, i1, i2, i3] = sum_l A[i0, i1, l] B[l, i2, i3] without forming C.  By
+ * linearity it is the sum over l of the Kronecker-product sketches of the
+ * slices A(:,:,l) and B(l,:,:); the spectra of the slice products are summed
+ * over l before one inverse transform per slice.  Each slice's order-2
+ * sketch is summed exactly in 64-bit fixed point as in fcs_sketch_kron.
+ *   plan  order-4 plan; modes 0, 1 index A's first two modes, 2, 3 B's last
+ *         two; (J_0 + J_1 - 1) and (J_2 + J_3 - 1) 64-bit bins fit in LDS
+ *   Lc    length of the shared index, 1 .. 2^20 (Lc = 1: the Kronecker
+ *         product of A(:,:,0) and B(0,:,:))
+ *   A     device, float, I_0 x I_1 x Lc column-major (mode 0 fastest)
+ *   B     device, float, Lc x I_2 x I_3 column-major (the shared index
+ *         fastest, so each slice B(l,:,:) is read with stride Lc)
+ *   out   device, float, D x J~; overwritten (may be NULL if spec is set)
+ *   spec  device, float2, D x fcs_plan_spec_len, or NULL
+ *   ws    device workspace of ws_bytes >=
+ *         fcs_workspace_bytes(FCS_OP_CONTRACTION, R = Lc), 16-byte aligned
+ * A slice with a non-finite entry gives a NaN sketch.
+ * Errors: FCS_EINVAL, FCS_ENOMEM, FCS_EUNSUPPORTED, FCS_EDEVICE. */
+FCS_API fcs_status fcs_sketch_contraction(fcs_plan_t plan, int64_t Lc, const float *A,
+                                          const float *B, float *out, float *spec, void *ws,
+                                          size_t ws_bytes, void *stream);
+
+/* Decompression, Section 4.3 (the rule stated there for the Kronecker
+ * product and the contraction, applied at any order): per sketch d, entry i
+ * of the recovered tensor is S_d(i) y_d[H_d(i)] with H_d = sum_n h_n(i_n)
+ * and S_d = prod_n s_n(i_n); out holds the median over the D sketches (mean
+ * of the middle pair for even D, formed in double and rounded once), so for
+ * odd D every entry equals one of its D estimates exactly.
+ *   y      device, float, D x J~ finite sketches of this plan
+ *   order  host array of N mode indices, the output's layout from the
+ *          fastest-varying mode outwards, or NULL for vec order (0, 1, ...,
+ *          N-1).  A (x) B of fcs_sketch_kron as the (I_0 I_2) x (I_1 I_3)
+ *          column-major matrix is order = {2, 0, 3, 1}
+ *   out    device, float, prod_n I_n entries; overwritten (16-byte
+ *          alignment and I_order[0] % 4 == 0 give vector stores)
+ * The call allocates nothing and needs no workspace.  D <= 32, every I_n
+ * < 2^31.
+ * Errors: FCS_EINVAL (null pointer, misalignment, order not a permutation),
+ * FCS_EUNSUPPORTED (D > 32, sizes out of range), FCS_EDEVICE. */
+FCS_API fcs_status fcs_decompress(fcs_plan_t plan, const float *y, const int32_t *order,
+                                  float *out, void *stream);
 
 /* Spectrum of existing sketches (for contractions of dense or COO sketches):
  *   y     device, float, D x J~

@@ -383,6 +383,21 @@ def decompress_median(Y, hs, ss, I) -> np.ndarray:
     return median(est, axis=0)
 
 
+def decompress_at(Y, hs, ss, idx) -> np.ndarray:
+    """The same recovered entries one by one: idx[n][k] is the mode-n index
+    of entry k; returns the median over d of S_d y_d[H_d] for each k."""
+    idx = [np.asarray(ix, dtype=np.int64) for ix in idx]
+    est = []
+    for d in range(len(Y)):
+        H = np.zeros(idx[0].shape, dtype=np.int64)
+        S = np.ones(idx[0].shape, dtype=np.float64)
+        for n, ix in enumerate(idx):
+            H += np.asarray(hs[d][n], dtype=np.int64)[ix]
+            S *= np.asarray(ss[d][n], dtype=np.float64)[ix]
+        est.append(S * np.asarray(Y[d], dtype=np.float64)[H])
+    return median(np.stack(est), axis=0)
+
+
 def kron_decompress(y, h, s, I) -> np.ndarray:
     """Entry (i1,i2,i3,i4) of the recovered order-4 tensor is
     s1 s2 s3 s4 * FCS[h1 + h2 + h3 + h4] (Section 4.3; 0-based, so the

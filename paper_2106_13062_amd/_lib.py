@@ -18,7 +18,7 @@ U64 = ctypes.c_uint64
 SZ = ctypes.c_size_t
 
 FCS_OK, FCS_EINVAL, FCS_ENOMEM, FCS_EADMIT, FCS_EDEVICE, FCS_EUNSUPPORTED = range(6)
-OP_DENSE, OP_COO, OP_CP, OP_INNER, OP_FREE_MODE, OP_SPECTRUM, OP_KRON = range(7)
+OP_DENSE, OP_COO, OP_CP, OP_INNER, OP_FREE_MODE, OP_SPECTRUM, OP_KRON, OP_CONTRACTION = range(8)
 ITEM_CP, ITEM_KRON = 0, 1
 NCLASS = 7
 MAX_ORDER, MAX_D, MAX_FFT = 8, 64, 16384
@@ -56,6 +56,8 @@ SIGNATURES = {
     "fcs_sketch_cp": (I32, [P, I64, ctypes.POINTER(P), P, P, P, P, SZ, P]),
     "fcs_sketch_spectrum": (I32, [P, P, P, P, SZ, P]),
     "fcs_sketch_kron": (I32, [P, P, P, P, P, P, SZ, P]),
+    "fcs_sketch_contraction": (I32, [P, I64, P, P, P, P, P, SZ, P]),
+    "fcs_decompress": (I32, [P, P, ctypes.POINTER(I32), P, P]),
     "fcs_batch_create": (I32, [ctypes.POINTER(BatchItem), I64, ctypes.POINTER(BatchConfig),
                                ctypes.POINTER(P)]),
     "fcs_batch_workspace_bytes": (SZ, [P]),

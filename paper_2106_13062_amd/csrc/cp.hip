@@ -89,6 +89,14 @@ __global__ __launch_bounds__(Shape<P>::T) void kron_kernel(CpDesc c) {
     kron_sketch<P>(c, blockIdx.x, lds);
 }
 
+// Contraction of two order-3 tensors over a shared index: one workgroup per
+// sketch.
+template <int P>
+__global__ __launch_bounds__(Shape<P>::T) void contraction_kernel(CpDesc c) {
+    extern __shared__ float2 lds[];
+    contraction_sketch<P>(c, blockIdx.x, lds);
+}
+
 // ---------------------------------------------------------------------------
 // Spectrum of given sketches: one workgroup per (sketch, slice).
 // ---------------------------------------------------------------------------
@@ -287,6 +295,13 @@ void launch_kron(const CpDesc &c, hipStream_t s) {
 }
 
 template <int P>
+void launch_contraction(const CpDesc &c, hipStream_t s) {
+    const size_t lds = cp_lds_bytes(P, c);
+    allow_lds_cp(contraction_kernel<P>, lds);
+    hipLaunchKernelGGL(contraction_kernel<P>, dim3(c.D), dim3(Shape<P>::T), lds, s, c);
+}
+
+template <int P>
 void launch_spectrum(const SpecArgs &sa, int D, int Qh, hipStream_t s) {
     constexpr size_t lds = Lds<P>::bytes;
     allow_lds_cp(spectrum_kernel<P>, lds);
@@ -323,6 +338,11 @@ size_t fcs_ws_cp(const fcs_plan *p, int64_t R) {
 size_t fcs_ws_kron(const fcs_plan *p) {
     if (p->N != 4) return 256;
     return align256((size_t)p->D * (p->J[0] + p->J[1] - 1 + p->J[2] + p->J[3] - 1) * sizeof(float));
+}
+
+size_t fcs_ws_contraction(const fcs_plan *p, int64_t Lc) {
+    if (p->N != 4 || Lc < 1) return 256;
+    return align256((size_t)p->D * (size_t)Lc * (p->J[0] + p->J[1] - 1 + p->J[2] + p->J[3] - 1) * sizeof(float));
 }
 
 size_t fcs_ws_spectrum(const fcs_plan *) { return 256; }
@@ -406,6 +426,38 @@ extern "C" fcs_status fcs_sketch_kron(fcs_plan_t p, const float *A, const float 
     c.spec = (float2 *)spec;
     hipStream_t s = (hipStream_t)stream;
     FCS_DISPATCH_FFT(p->P, (launch_kron<PP>(c, s)));
+    FCS_LAUNCH_CHECK();
+    return FCS_OK;
+}
+
+extern "C" fcs_status fcs_sketch_contraction(fcs_plan_t p, int64_t Lc, const float *A, const float *B,
+                                             float *out, float *spec, void *ws, size_t ws_bytes, void *stream) {
+    fcs_clear_error();
+    if (!p || !p->bound) FCS_FAIL(FCS_EINVAL, "plan is null or not bound");
+    if (p->N != 4) FCS_FAIL(FCS_EINVAL, "a contraction sketch needs an order-4 plan (N=%d)", p->N);
+    if (p->P == 0) FCS_FAIL(FCS_EUNSUPPORTED, "no transform length fits this plan");
+    if (Lc < 1 || Lc > (1 << 20)) FCS_FAIL(FCS_EINVAL, "shared index length %lld out of range", (long long)Lc);
+    if (!A || !B) FCS_FAIL(FCS_EINVAL, "null factor tensor");
+    if (!out && !spec) FCS_FAIL(FCS_EINVAL, "neither out nor spec given");
+    CpDesc c{};
+    desc_from_plan(c, p);
+    c.kind = FCS_DESC_CONTRACTION;
+    if (cp_lds_bytes((int)p->P, c) > FCS_LDS_BYTES - 1024)
+        FCS_FAIL(FCS_EUNSUPPORTED, "factor sketches of %d and %d bins exceed LDS", c.J[0] + c.J[1] - 1,
+                 c.J[2] + c.J[3] - 1);
+    const size_t need = fcs_ws_contraction(p, Lc);
+    if (!ws || ws_bytes < need) FCS_FAIL(FCS_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, need);
+    if (!fcs_aligned(ws, 16)) FCS_FAIL(FCS_EINVAL, "workspace not 16-byte aligned");
+    c.U[0] = A;
+    c.U[1] = B;
+    c.R = (int)Lc;
+    c.nchunks = 1;
+    c.rchunk = 1;
+    c.kscratch = (float *)ws;
+    c.out = out;
+    c.spec = (float2 *)spec;
+    hipStream_t s = (hipStream_t)stream;
+    FCS_DISPATCH_FFT(p->P, (launch_contraction<PP>(c, s)));
     FCS_LAUNCH_CHECK();
     return FCS_OK;
 }

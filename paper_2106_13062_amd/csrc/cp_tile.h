@@ -260,11 +260,11 @@ __device__ __forceinline__ void stage_column(float *dst, const float *__restrict
 }
 
 // One CP (or Kronecker) sketch computation as the kernels see it.
-enum { FCS_DESC_CP = 0, FCS_DESC_KRON = 1 };
+enum { FCS_DESC_CP = 0, FCS_DESC_KRON = 1, FCS_DESC_CONTRACTION = 2 };
 
 struct CpDesc {
-    int kind;                        // FCS_DESC_CP or FCS_DESC_KRON
-    int N, D, R;
+    int kind;                        // FCS_DESC_CP, FCS_DESC_KRON or FCS_DESC_CONTRACTION
+    int N, D, R;                     // CONTRACTION: R = length of the shared index
     int nchunks, rchunk;             // rank chunks of the forward tiles
     int I[FCS_MAX_ORDER];
     int J[FCS_MAX_ORDER];
@@ -281,6 +281,7 @@ struct CpDesc {
     float2 *partial;                 // [D][Qh][nchunks][P] forward partial spectra (nchunks > 1)
     float *ytmp;                     // [D][Qh][Jt] inverse term of every slice (Qh > 1)
     float *kscratch;                 // KRON: [D][J_0 + J_1 - 1 + J_2 + J_3 - 1] factor sketches
+                                     // CONTRACTION: [D][R][the same] (one pair per shared index)
     float *out;                      // D x Jt or null
     float2 *spec;                    // D x (Qh * P) or null
     int cnt_slice;                   // batch: first (d, q) chunk counter (nchunks > 1)
@@ -419,11 +420,13 @@ __device__ __forceinline__ void sum_slices(const CpDesc &c, int d) {
 // Entries are quantised to integers (the largest magnitude maps into
 // [2^27, 2^28)) and summed exactly in 64-bit LDS bins; lds must hold nb
 // 64-bit words.  A matrix with a non-finite entry gives NaN bins.
-template <int T>
+// With STRIDED, entry k of the matrix is M[k * stride] (a slice of a
+// larger tensor whose other index varies fastest).
+template <int T, bool STRIDED = false>
 __device__ __forceinline__ void kron_factor_sketch(const float *__restrict__ M, int Ia, int Ib,
                                                    const uint32_t *__restrict__ ta,
                                                    const uint32_t *__restrict__ tb, int nb, float *y,
-                                                   float2 *lds) {
+                                                   float2 *lds, int64_t stride = 1) {
     unsigned long long *bins = reinterpret_cast<unsigned long long *>(lds);
     float *red = reinterpret_cast<float *>(lds);
     const int t = tid_opaque();
@@ -431,7 +434,7 @@ __device__ __forceinline__ void kron_factor_sketch(const float *__restrict__ M, 
     float m = 0.f;
     bool bad = false;
     for (int64_t k = t; k < n; k += T) {
-        const float v = fabsf(M[k]);
+        const float v = fabsf(M[STRIDED ? k * stride : k]);
         bad |= !(v <= 3.4e38f);
         m = fmaxf(m, v);
     }
@@ -468,7 +471,7 @@ __device__ __forceinline__ void kron_factor_sketch(const float *__restrict__ M, 
     for (int64_t k = t; k < n; k += T) {
         const uint32_t wa = ta[i], wb = tb[j];
         const int bin = (int)(wa & FCS_H_MASK) + (int)(wb & FCS_H_MASK);
-        long long qv = (long long)__float2int_rn(M[k] * scale);
+        long long qv = (long long)__float2int_rn(M[STRIDED ? k * stride : k] * scale);
         if ((wa ^ wb) & FCS_S_BIT) qv = -qv;
         atomicAdd(&bins[bin], (unsigned long long)qv);
         i += st_i;
@@ -513,6 +516,49 @@ __device__ __forceinline__ void kron_sketch(const CpDesc &c, int d, float2 *lds)
     }
 }
 
+// Contraction C[i0,i1,i2,i3] = sum_l A[i0,i1,l] B[l,i2,i3] of an
+// I_0 x I_1 x R tensor A with an R x I_2 x I_3 tensor B (both column-major,
+// Section 4.3): FCS(C) = sum_l F^-1(F(FCS(A(:,:,l))) F(FCS(B(l,:,:)))).  By
+// linearity the products of the slice spectra are summed over l before one
+// inverse per transform slice.  The order-2 sketches of every A(:,:,l) and
+// B(l,:,:) (a stride-R slice) go to the workspace first.
+template <int P>
+__device__ __forceinline__ void contraction_sketch(const CpDesc &c, int d, float2 *lds) {
+    constexpr int E = Shape<P>::E;
+    constexpr int T = Shape<P>::T;
+    const uint32_t *tab = c.tab + (int64_t)d * c.sumI;
+    const int na = c.J[0] + c.J[1] - 1;
+    const int nbb = c.J[2] + c.J[3] - 1;
+    const int64_t sa = (int64_t)c.I[0] * c.I[1];
+    float *ys = c.kscratch + (int64_t)d * c.R * (na + nbb);
+    for (int l = 0; l < c.R; ++l) {
+        float *ya = ys + (int64_t)l * (na + nbb);
+        kron_factor_sketch<T>(c.U[0] + l * sa, c.I[0], c.I[1], tab + c.off[0], tab + c.off[1], na, ya, lds);
+        kron_factor_sketch<T, true>(c.U[1] + l, c.I[2], c.I[3], tab + c.off[2], tab + c.off[3], nbb, ya + na,
+                                    lds, c.R);
+    }
+    __threadfence_block();
+    __syncthreads();
+    for (int q = 0; q < c.s.Qh; ++q) {
+        float2 acc[E];
+        for (int l = 0; l < c.R; ++l) {
+            const float *ya = ys + (int64_t)l * (na + nbb);
+            float2 X[E];
+            build_seq_slice<P>(X, ya, na, q, c.s);
+            forward_regs<P>(lds, c.s.twP, X);
+            float2 Y[E];
+            build_seq_slice<P>(Y, ya + na, nbb, q, c.s);
+            forward_regs<P>(lds, c.s.twP, Y);
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const float2 xy = cmul(X[e], Y[e]);
+                acc[e] = l == 0 ? xy : make_float2(acc[e].x + xy.x, acc[e].y + xy.y);
+            }
+        }
+        finish_slice<P>(c, d, q, lds, acc, c.out ? c.out + (int64_t)d * c.Jt : nullptr, q > 0);
+    }
+}
+
 // Plan-derived part of a descriptor (host side).
 inline SliceArgs slice_args(const fcs_plan *p) {
     SliceArgs s;
@@ -545,7 +591,7 @@ inline void desc_from_plan(CpDesc &c, const fcs_plan *p) {
 // LDS bytes a kernel of FFT size P needs for a computation.
 __host__ __device__ inline size_t cp_lds_bytes(int P, const CpDesc &c) {
     size_t b = (size_t)(P + P / 16) * 8;
-    if (c.kind == FCS_DESC_KRON) {
+    if (c.kind == FCS_DESC_KRON || c.kind == FCS_DESC_CONTRACTION) {
         const size_t na = (size_t)(c.J[0] + c.J[1] - 1), nb = (size_t)(c.J[2] + c.J[3] - 1);
         b = na * 8 > b ? na * 8 : b;
         b = nb * 8 > b ? nb * 8 : b;

@@ -166,6 +166,52 @@ class Plan:
                                          _stream(stream)))
         return out, spec
 
+    def sketch_contraction(self, A: torch.Tensor, B: torch.Tensor, out=None, spec=None, want_out=True,
+                           want_spec=False, ws=None, stream=None):
+        """Contraction sum_l A[i0, i1, l] B[l, i2, i3] of an order-4 plan: A
+        is I_0 x I_1 x Lc and B is Lc x I_2 x I_3, each a float32 tensor in
+        column-major order (shape (Lc, I_1, I_0), resp. (I_3, I_2, Lc))."""
+        if self.N != 4:
+            raise ValueError("a contraction sketch needs an order-4 plan")
+        _need(A, torch.float32, "A")
+        _need(B, torch.float32, "B")
+        sa, sb = self.I[0] * self.I[1], self.I[2] * self.I[3]
+        if A.numel() == 0 or A.numel() % sa != 0:
+            raise ValueError("A must have I_0 * I_1 * Lc entries")
+        Lc = A.numel() // sa
+        if B.numel() != Lc * sb:
+            raise ValueError("B must have Lc * I_2 * I_3 entries")
+        if want_out and out is None:
+            out = torch.empty((self.D, self.Jt), dtype=torch.float32, device=self.device)
+        if want_spec and spec is None:
+            spec = torch.empty((self.D, self.spec_len, 2), dtype=torch.float32, device=self.device)
+        ws, nb = self._ws(ws, C.OP_CONTRACTION, R=Lc)
+        C.check(self.lib.fcs_sketch_contraction(self._h, Lc, _ptr(A), _ptr(B), _ptr(out), _ptr(spec), _ptr(ws),
+                                                nb, _stream(stream)))
+        return out, spec
+
+    def decompress(self, y: torch.Tensor, order=None, out=None, stream=None) -> torch.Tensor:
+        """Recovered tensor (median over the D sketches) as a flat float32
+        tensor of prod I_n entries, laid out with mode order[0] fastest
+        (vec order when order is None)."""
+        _need(y, torch.float32, "y")
+        if tuple(y.shape) != (self.D, self.Jt):
+            raise ValueError("y must be D x J~")
+        n = 1
+        for i in self.I:
+            n *= i
+        out = torch.empty(n, dtype=torch.float32, device=self.device) if out is None else out
+        _need(out, torch.float32, "out")
+        if out.numel() != n:
+            raise ValueError("out must have prod I_n entries")
+        ords = None
+        if order is not None:
+            if len(order) != self.N:
+                raise ValueError("order must list every mode once")
+            ords = (ctypes.c_int32 * self.N)(*[int(k) for k in order])
+        C.check(self.lib.fcs_decompress(self._h, _ptr(y), ords, _ptr(out), _stream(stream)))
+        return out
+
     def spectrum(self, y: torch.Tensor, spec=None, ws=None, stream=None):
         _need(y, torch.float32, "y")
         spec = torch.empty((self.D, self.spec_len, 2), dtype=torch.float32, device=self.device) \

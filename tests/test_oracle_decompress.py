@@ -82,3 +82,12 @@ def test_contraction_sketch_is_fcs_of_the_contraction():
     # one shared index is the Kronecker product
     np.testing.assert_allclose(O.contraction_fcs(A[:, :, :1], B[:1], hs[0], ss[0], J),
                                O.kron_fcs(A[:, :, 0], B[0], hs[0], ss[0], J), rtol=0, atol=1e-12)
+
+
+def test_decompress_at_equals_the_whole_tensor():
+    I, J, D = (5, 3, 4), (7, 6, 5), 4
+    hs, ss = O.hash_tables(55, D, I, J)
+    Y = np.random.default_rng(12).standard_normal((D, O.sketch_length(J)))
+    full = O.decompress_median(Y, hs, ss, I)
+    grid = np.indices(I).reshape(3, -1)
+    np.testing.assert_array_equal(O.decompress_at(Y, hs, ss, grid), full.reshape(-1))
