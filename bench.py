@@ -489,6 +489,66 @@ def als_workload(args, torch, dev):
             "weights": [round(float(x), 5) for x in lam.cpu()]}
 
 
+def decompress_workload(args, torch, dev):
+    """Decompression (Section 4.3) of the Kronecker product of two 256 x 256
+    U[-5, 5] matrices: 2^32 recovered entries (16 GiB) written as the
+    column-major (I_0 I_2) x (I_1 I_3) matrix, J_n = 4096, D = 1, 3 and 20
+    sketches (median over D).  Timed with HIP events on the launch stream;
+    algorithmic HBM bytes per launch are the output (4 B per entry) plus one
+    read of the sketches and hash words.  Also, end to end on the paper's
+    set-ups with D = 20 and J_n = 4096: the Kronecker product of A 30 x 40
+    and B 40 x 50, and the contraction of A 30 x 40 x 50 with B 50 x 40 x 30
+    over the shared index (compression, then decompression)."""
+    import synth
+    from paper_2106_13062_amd import Plan
+    stream = torch.cuda.current_stream()
+    I, J = (256, 256, 256, 256), (4096, 4096, 4096, 4096)
+    g = synth.rng(synth.DATA_SEED["batch4096"], 31)
+    A = torch.from_numpy(g.uniform(-5, 5, 256 * 256).astype(np.float32)).to(dev)
+    B = torch.from_numpy(g.uniform(-5, 5, 256 * 256).astype(np.float32)).to(dev)
+    M = 1 << 32
+    out = torch.empty(M, dtype=torch.float32, device=dev)
+    runs = []
+    for D in (1, 3, 20):
+        plan = Plan(I, J, D, synth.HASH_SEED["batch4096"] + D, device=dev)
+        y, _ = plan.sketch_kron(A, B)
+
+        def step():
+            plan.decompress(y, order=(2, 0, 3, 1), out=out, stream=stream)
+
+        step()
+        ms, _ = event_timer(torch, stream, step, max(3, args.steps // 4))
+        nbytes = 4.0 * M + 4.0 * D * plan.Jt + 4.0 * D * sum(I)
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        runs.append({"D": D, "ms": ms, "entries_per_s": M / (ms * 1e-3), "GB_per_s": gbs,
+                     "frac_hbm": gbs / HBM_PEAK_GBS, "bytes_per_launch": nbytes})
+        plan.close()
+    del out
+    torch.cuda.empty_cache()
+    # the paper's set-ups, compression and decompression, D = 20
+    D, Jp = 20, (4096, 4096, 4096, 4096)
+    Ak = torch.from_numpy(g.uniform(-5, 5, 30 * 40).astype(np.float32)).to(dev)
+    Bk = torch.from_numpy(g.uniform(-5, 5, 40 * 50).astype(np.float32)).to(dev)
+    pk = Plan((30, 40, 40, 50), Jp, D, 77, device=dev)
+    outk = torch.empty(30 * 40 * 40 * 50, dtype=torch.float32, device=dev)
+    wsk = pk.workspace(6)
+    yk = torch.empty((D, pk.Jt), dtype=torch.float32, device=dev)
+    kc, _ = event_timer(torch, stream, lambda: pk.sketch_kron(Ak, Bk, out=yk, ws=wsk, stream=stream), 5)
+    kd, _ = event_timer(torch, stream, lambda: pk.decompress(yk, order=(2, 0, 3, 1), out=outk, stream=stream), 5)
+    Ac = torch.from_numpy(g.uniform(0, 10, 30 * 40 * 50).astype(np.float32)).to(dev)
+    Bc = torch.from_numpy(g.uniform(0, 10, 50 * 40 * 30).astype(np.float32)).to(dev)
+    pc = Plan((30, 40, 40, 30), Jp, D, 78, device=dev)
+    outc = torch.empty(30 * 40 * 40 * 30, dtype=torch.float32, device=dev)
+    wsc = pc.workspace(7, R=50)
+    yc = torch.empty((D, pc.Jt), dtype=torch.float32, device=dev)
+    cc, _ = event_timer(torch, stream, lambda: pc.sketch_contraction(Ac, Bc, out=yc, ws=wsc, stream=stream), 5)
+    cd, _ = event_timer(torch, stream, lambda: pc.decompress(yc, out=outc, stream=stream), 5)
+    return {"workload": "decompress256: A (x) B of two 256 x 256 matrices, 2^32 entries (16 GiB) in matrix "
+                        "layout, J_n=4096", "runs": runs,
+            "paper_kron_30x40_40x50_D20": {"compress_ms": kc, "decompress_ms": kd},
+            "paper_contraction_30x40x50_50x40x30_D20": {"compress_ms": cc, "decompress_ms": cd}}
+
+
 def serve_workload(args, torch, dev):
     """Poisson request streams at several rates through the continuous
     batching server, against the same requests served one at a time."""
@@ -566,7 +626,7 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=1 << 19,
                     help="rows of the tensor the CPU oracle sketches")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "dense1024_traffic.json"))
-    ap.add_argument("--mode", default="full", choices=["full", "dense", "cp", "batch", "serve", "rtpm", "als", "copy"],
+    ap.add_argument("--mode", default="full", choices=["full", "dense", "cp", "batch", "serve", "rtpm", "als", "decompress", "copy"],
                     help="full: headline + secondary workloads; dense: headline only; cp: the CP "
                          "sketches and T(I,u,v) only; batch: the uneven batch only; serve: the "
                          "serving loop only; copy: plain copy kernel for counter calibration")
@@ -606,6 +666,9 @@ def main():
     if args.mode == "als":
         print(json.dumps({"als": als_workload(args, torch, dev)}), flush=True)
         return
+    if args.mode == "decompress":
+        print(json.dumps({"decompress": decompress_workload(args, torch, dev)}), flush=True)
+        return
     if args.mode == "cp":
         import synth
         print(json.dumps({"cp100": cp_workload(args, torch, dev, synth.CP100),
@@ -633,6 +696,9 @@ def main():
         secondary["rtpm"] = rtpm_workload(args, torch, dev)
         log("secondary: sketched ALS")
         secondary["als"] = als_workload(args, torch, dev)
+        torch.cuda.empty_cache()
+        log("secondary: decompression and contraction compression")
+        secondary["decompress"] = decompress_workload(args, torch, dev)
     del T
     # HBM traffic per launch from the committed FETCH_SIZE / WRITE_SIZE
     # summary, only while the kernel source is the one that was measured

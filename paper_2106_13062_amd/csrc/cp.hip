@@ -89,12 +89,29 @@ __global__ __launch_bounds__(Shape<P>::T) void kron_kernel(CpDesc c) {
     kron_sketch<P>(c, blockIdx.x, lds);
 }
 
-// Contraction of two order-3 tensors over a shared index: one workgroup per
-// sketch.
+// Contraction of two order-3 tensors over a shared index: the slice sketches
+// (one workgroup per sketch and shared index), then forward tiles over
+// chunks of the shared index laid out like the CP rank chunks, so the CP
+// chunk reduction and finalisation complete it.
 template <int P>
-__global__ __launch_bounds__(Shape<P>::T) void contraction_kernel(CpDesc c) {
+__global__ __launch_bounds__(Shape<P>::T) void contraction_factor_kernel(CpDesc c) {
     extern __shared__ float2 lds[];
-    contraction_sketch<P>(c, blockIdx.x, lds);
+    contraction_factors<Shape<P>::T>(c, blockIdx.x / c.R, blockIdx.x % c.R, lds);
+}
+
+template <int P>
+__global__ __launch_bounds__(Shape<P>::T) void contraction_forward_kernel(CpDesc c) {
+    extern __shared__ float2 lds[];
+    const int tile = blockIdx.x;
+    const int chunk = tile % c.nchunks;
+    const int q = (tile / c.nchunks) % c.s.Qh;
+    const int d = tile / (c.nchunks * c.s.Qh);
+    float2 acc[Shape<P>::E];
+    contraction_tile<P>(c, d, q, chunk, lds, acc);
+    if (c.nchunks == 1)
+        finish_slice<P>(c, d, q, lds, acc, slice_dst(c, d, q), false);
+    else
+        store_partial<P>(c, d, q, chunk, acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -297,8 +314,22 @@ void launch_kron(const CpDesc &c, hipStream_t s) {
 template <int P>
 void launch_contraction(const CpDesc &c, hipStream_t s) {
     const size_t lds = cp_lds_bytes(P, c);
-    allow_lds_cp(contraction_kernel<P>, lds);
-    hipLaunchKernelGGL(contraction_kernel<P>, dim3(c.D), dim3(Shape<P>::T), lds, s, c);
+    constexpr size_t flds = Lds<P>::bytes;
+    allow_lds_cp(contraction_factor_kernel<P>, lds);
+    allow_lds_cp(contraction_forward_kernel<P>, flds);
+    allow_lds_cp(cp_finalize_kernel<P>, flds);
+    hipLaunchKernelGGL(contraction_factor_kernel<P>, dim3(c.D * c.R), dim3(Shape<P>::T), lds, s, c);
+    hipLaunchKernelGGL(contraction_forward_kernel<P>, dim3(c.D * c.s.Qh * c.nchunks), dim3(Shape<P>::T), flds, s,
+                       c);
+    if (c.nchunks > 1) {
+        const int blocks = P / 256;
+        hipLaunchKernelGGL(reduce_chunks_kernel, dim3(c.D * c.s.Qh * blocks), dim3(256), 0, s, c.partial,
+                           c.nchunks, P, blocks);
+        hipLaunchKernelGGL(cp_finalize_kernel<P>, dim3(c.D * c.s.Qh), dim3(Shape<P>::T), flds, s, c);
+    }
+    if (c.s.Qh > 1 && c.out)
+        hipLaunchKernelGGL(sum_slices_kernel, dim3((unsigned)fcs_ceil_div((int64_t)c.D * c.Jt, 256)), dim3(256), 0,
+                           s, c);
 }
 
 template <int P>
@@ -340,9 +371,15 @@ size_t fcs_ws_kron(const fcs_plan *p) {
     return align256((size_t)p->D * (p->J[0] + p->J[1] - 1 + p->J[2] + p->J[3] - 1) * sizeof(float));
 }
 
-size_t fcs_ws_contraction(const fcs_plan *p, int64_t Lc) {
-    if (p->N != 4 || Lc < 1) return 256;
+// contraction workspace: slice sketches, then the CP chunk partials and
+// slice terms for chunks of the shared index
+static size_t contraction_factor_bytes(const fcs_plan *p, int64_t Lc) {
     return align256((size_t)p->D * (size_t)Lc * (p->J[0] + p->J[1] - 1 + p->J[2] + p->J[3] - 1) * sizeof(float));
+}
+
+size_t fcs_ws_contraction(const fcs_plan *p, int64_t Lc) {
+    if (p->N != 4 || Lc < 1 || p->P == 0) return 256;
+    return contraction_factor_bytes(p, Lc) + cp_partial_bytes(p, cp_chunks(p, Lc)) + cp_ytmp_bytes(p);
 }
 
 size_t fcs_ws_spectrum(const fcs_plan *) { return 256; }
@@ -451,9 +488,11 @@ extern "C" fcs_status fcs_sketch_contraction(fcs_plan_t p, int64_t Lc, const flo
     c.U[0] = A;
     c.U[1] = B;
     c.R = (int)Lc;
-    c.nchunks = 1;
-    c.rchunk = 1;
+    c.nchunks = cp_chunks(p, Lc);
+    c.rchunk = (int)fcs_ceil_div(Lc, c.nchunks);
     c.kscratch = (float *)ws;
+    c.partial = (float2 *)((char *)ws + contraction_factor_bytes(p, Lc));
+    c.ytmp = (float *)((char *)c.partial + cp_partial_bytes(p, c.nchunks));
     c.out = out;
     c.spec = (float2 *)spec;
     hipStream_t s = (hipStream_t)stream;

@@ -281,7 +281,8 @@ struct CpDesc {
     float2 *partial;                 // [D][Qh][nchunks][P] forward partial spectra (nchunks > 1)
     float *ytmp;                     // [D][Qh][Jt] inverse term of every slice (Qh > 1)
     float *kscratch;                 // KRON: [D][J_0 + J_1 - 1 + J_2 + J_3 - 1] factor sketches
-                                     // CONTRACTION: [D][R][the same] (one pair per shared index)
+                                     // CONTRACTION: [D][R][the same] (one pair per shared index);
+                                     // rank chunks are chunks of the shared index
     float *out;                      // D x Jt or null
     float2 *spec;                    // D x (Qh * P) or null
     int cnt_slice;                   // batch: first (d, q) chunk counter (nchunks > 1)
@@ -520,42 +521,45 @@ __device__ __forceinline__ void kron_sketch(const CpDesc &c, int d, float2 *lds)
 // I_0 x I_1 x R tensor A with an R x I_2 x I_3 tensor B (both column-major,
 // Section 4.3): FCS(C) = sum_l F^-1(F(FCS(A(:,:,l))) F(FCS(B(l,:,:)))).  By
 // linearity the products of the slice spectra are summed over l before one
-// inverse per transform slice.  The order-2 sketches of every A(:,:,l) and
-// B(l,:,:) (a stride-R slice) go to the workspace first.
-template <int P>
-__device__ __forceinline__ void contraction_sketch(const CpDesc &c, int d, float2 *lds) {
-    constexpr int E = Shape<P>::E;
-    constexpr int T = Shape<P>::T;
+// inverse per transform slice.
+//
+// First step, one workgroup per (sketch d, shared index l): the order-2
+// sketches of A(:,:,l) and of B(l,:,:) (a stride-R slice) into the
+// workspace, [D][R][J_0 + J_1 - 1 + J_2 + J_3 - 1].
+template <int T>
+__device__ __forceinline__ void contraction_factors(const CpDesc &c, int d, int l, float2 *lds) {
     const uint32_t *tab = c.tab + (int64_t)d * c.sumI;
     const int na = c.J[0] + c.J[1] - 1;
     const int nbb = c.J[2] + c.J[3] - 1;
-    const int64_t sa = (int64_t)c.I[0] * c.I[1];
-    float *ys = c.kscratch + (int64_t)d * c.R * (na + nbb);
-    for (int l = 0; l < c.R; ++l) {
-        float *ya = ys + (int64_t)l * (na + nbb);
-        kron_factor_sketch<T>(c.U[0] + l * sa, c.I[0], c.I[1], tab + c.off[0], tab + c.off[1], na, ya, lds);
-        kron_factor_sketch<T, true>(c.U[1] + l, c.I[2], c.I[3], tab + c.off[2], tab + c.off[3], nbb, ya + na,
-                                    lds, c.R);
-    }
-    __threadfence_block();
-    __syncthreads();
-    for (int q = 0; q < c.s.Qh; ++q) {
-        float2 acc[E];
-        for (int l = 0; l < c.R; ++l) {
-            const float *ya = ys + (int64_t)l * (na + nbb);
-            float2 X[E];
-            build_seq_slice<P>(X, ya, na, q, c.s);
-            forward_regs<P>(lds, c.s.twP, X);
-            float2 Y[E];
-            build_seq_slice<P>(Y, ya + na, nbb, q, c.s);
-            forward_regs<P>(lds, c.s.twP, Y);
+    float *ya = c.kscratch + ((int64_t)d * c.R + l) * (na + nbb);
+    kron_factor_sketch<T>(c.U[0] + (int64_t)l * c.I[0] * c.I[1], c.I[0], c.I[1], tab + c.off[0], tab + c.off[1],
+                          na, ya, lds);
+    kron_factor_sketch<T, true>(c.U[1] + l, c.I[2], c.I[3], tab + c.off[2], tab + c.off[3], nbb, ya + na, lds,
+                                c.R);
+}
+
+// Second step, forward tile (sketch d, slice q, chunk of shared indices):
+// acc = sum over the chunk of F_q(sketch of A(:,:,l)) F_q(sketch of B(l,:,:)).
+template <int P>
+__device__ __forceinline__ void contraction_tile(const CpDesc &c, int d, int q, int chunk, float2 *lds,
+                                                 float2 (&acc)[Shape<P>::E]) {
+    constexpr int E = Shape<P>::E;
+    const int na = c.J[0] + c.J[1] - 1;
+    const int nbb = c.J[2] + c.J[3] - 1;
+    const int l0 = chunk * c.rchunk;
+    const int l1 = min(c.R, l0 + c.rchunk);
 #pragma unroll
-            for (int e = 0; e < E; ++e) {
-                const float2 xy = cmul(X[e], Y[e]);
-                acc[e] = l == 0 ? xy : make_float2(acc[e].x + xy.x, acc[e].y + xy.y);
-            }
-        }
-        finish_slice<P>(c, d, q, lds, acc, c.out ? c.out + (int64_t)d * c.Jt : nullptr, q > 0);
+    for (int e = 0; e < E; ++e) acc[e] = make_float2(0.f, 0.f);
+    for (int l = l0; l < l1; ++l) {
+        const float *ya = c.kscratch + ((int64_t)d * c.R + l) * (na + nbb);
+        float2 X[E];
+        build_seq_slice<P>(X, ya, na, q, c.s);
+        forward_regs<P>(lds, c.s.twP, X);
+        float2 Y[E];
+        build_seq_slice<P>(Y, ya + na, nbb, q, c.s);
+        forward_regs<P>(lds, c.s.twP, Y);
+#pragma unroll
+        for (int e = 0; e < E; ++e) acc[e] = cadd(acc[e], cmul(X[e], Y[e]));
     }
 }
 

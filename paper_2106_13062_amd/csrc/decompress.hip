@@ -15,9 +15,10 @@
 // stages the D windows in LDS with the row's sign applied.  After that, each
 // entry costs one LDS read per sketch, the median, and its share of a 16-byte
 // non-temporal store.  The kernel is therefore bound by HBM writes for small
-// D and by the median's ALU work for large D.  Where the windows would not
-// fit in LDS, or a row is shorter than its staged windows, entries read y
-// from global memory instead; y is D x J~ floats and stays resident in L2.
+// D.  Where the D windows would not fit in LDS, or a row is shorter than its
+// staged windows, entries read y from global memory in place; y is D x J~
+// floats and stays resident in L2, and the kernel is bound by those random
+// L2 reads.
 //
 // Packed hash words (bits 0..30 the hash, bit 31 the sign) add as words: a
 // sum of hashes stays below J~ < 2^31, so bit 31 of the word sum is the XOR
@@ -28,7 +29,8 @@
 
 namespace {
 
-constexpr int DC_T = 512;
+constexpr int DC_T = 512;                   // threads of the in-place and larger-D kernels
+constexpr int DC_T_SMALL = 1024;            // staged kernels with D <= 4
 constexpr int64_t DC_LDS_FLOATS = 36864;    // 144 KB of staged windows
 constexpr int DC_MAXD = 32;
 constexpr int64_t DC_ROW_TARGET = 65536;    // inner entries per row worth aiming for
@@ -102,8 +104,8 @@ __device__ __forceinline__ float estimate(const DecompArgs &a, const float *win,
     return __uint_as_float(__float_as_uint(v) ^ (word & FCS_S_BIT));
 }
 
-template <int MAXD, bool VEC, bool GLOBAL>
-__global__ __launch_bounds__(DC_T) void decompress_kernel(DecompArgs a) {
+template <int MAXD, bool VEC, bool GLOBAL, int T>
+__global__ __launch_bounds__(T) void decompress_kernel(DecompArgs a) {
     extern __shared__ float win[];           // D x W staged windows
     __shared__ uint32_t rowb[FCS_MAX_D];     // row hash word of each sketch
     const int t = threadIdx.x;
@@ -128,13 +130,13 @@ __global__ __launch_bounds__(DC_T) void decompress_kernel(DecompArgs a) {
             const uint32_t sg = rb & FCS_S_BIT;
             float *dst = win + d * a.W;
 #pragma unroll 4
-            for (int w = t; w < a.W; w += DC_T) dst[w] = __uint_as_float(__float_as_uint(src[w]) ^ sg);
+            for (int w = t; w < a.W; w += T) dst[w] = __uint_as_float(__float_as_uint(src[w]) ^ sg);
         }
         __syncthreads();
     }
     float *orow = a.out + (int64_t)r * a.n_in;
     if constexpr (VEC) {
-        for (uint32_t e = c0 + 4 * t; e < c1; e += 4 * DC_T) {
+        for (uint32_t e = c0 + 4 * t; e < c1; e += 4 * T) {
             const uint32_t j0 = e % a.n[0];
             uint32_t rem = e / a.n[0];
             uint32_t base[MAXD];
@@ -161,7 +163,7 @@ __global__ __launch_bounds__(DC_T) void decompress_kernel(DecompArgs a) {
             __builtin_nontemporal_store(o, reinterpret_cast<f32x4 *>(orow + e));
         }
     } else {
-        for (uint32_t e = c0 + t; e < c1; e += DC_T) {
+        for (uint32_t e = c0 + t; e < c1; e += T) {
             uint32_t rem = e;
             uint32_t word[MAXD];
 #pragma unroll
@@ -181,21 +183,22 @@ __global__ __launch_bounds__(DC_T) void decompress_kernel(DecompArgs a) {
     }
 }
 
-template <int MAXD, bool VEC, bool GLOBAL>
+template <int MAXD, bool VEC, bool GLOBAL, int T>
 void launch(const DecompArgs &a, uint32_t grid, size_t lds, hipStream_t s) {
-    auto k = decompress_kernel<MAXD, VEC, GLOBAL>;
+    auto k = decompress_kernel<MAXD, VEC, GLOBAL, T>;
     fcs_allow_lds((const void *)k, lds);
-    hipLaunchKernelGGL(k, dim3(grid), dim3(DC_T), lds, s, a);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(T), lds, s, a);
 }
 
 template <int MAXD>
-void launch_d(const DecompArgs &a, bool vec, bool global, uint32_t grid, size_t lds, hipStream_t s) {
+void launch_d(const DecompArgs &a, bool global, bool vec, uint32_t grid, size_t lds, hipStream_t s) {
+    constexpr int TS = MAXD <= 4 ? DC_T_SMALL : DC_T;
     if (vec) {
-        if (global) launch<MAXD, true, true>(a, grid, lds, s);
-        else launch<MAXD, true, false>(a, grid, lds, s);
+        if (global) launch<MAXD, true, true, DC_T>(a, grid, lds, s);
+        else launch<MAXD, true, false, TS>(a, grid, lds, s);
     } else {
-        if (global) launch<MAXD, false, true>(a, grid, lds, s);
-        else launch<MAXD, false, false>(a, grid, lds, s);
+        if (global) launch<MAXD, false, true, DC_T>(a, grid, lds, s);
+        else launch<MAXD, false, false, TS>(a, grid, lds, s);
     }
 }
 
@@ -247,21 +250,27 @@ extern "C" fcs_status fcs_decompress(fcs_plan_t p, const float *y, const int32_t
         return n;
     };
     const int64_t D = p->D;
-    bool global = D * W_of(1) > DC_LDS_FLOATS;
-    int ks = 1;
-    while (ks < N && nin_of(ks) < DC_ROW_TARGET && nin_of(ks + 1) < ((int64_t)1 << 31) &&
-           (global || D * W_of(ks + 1) <= DC_LDS_FLOATS))
-        ++ks;
-    // a row shorter than its staged windows reads y in place instead
-    if (!global && nin_of(ks) < D * W_of(ks)) {
-        global = true;
-        while (ks < N && nin_of(ks) < DC_ROW_TARGET && nin_of(ks + 1) < ((int64_t)1 << 31)) ++ks;
+    const bool vec = (I[0] % 4 == 0) && fcs_aligned(out, 16);
+    auto grow = [&](auto fits) {
+        int ks = 1;
+        while (ks < N && nin_of(ks) < DC_ROW_TARGET && nin_of(ks + 1) < ((int64_t)1 << 31) && fits(ks + 1))
+            ++ks;
+        return ks;
+    };
+    // the D windows staged in LDS, if they fit and a row is long enough to
+    // repay the staging; otherwise entries read y in place
+    bool global = true;
+    int ks = 0;
+    if (D * W_of(1) <= DC_LDS_FLOATS) {
+        ks = grow([&](int k) { return D * W_of(k) <= DC_LDS_FLOATS; });
+        global = nin_of(ks) < D * W_of(ks);
     }
+    if (global) ks = grow([](int) { return true; });
     const int64_t n_in = nin_of(ks);
     const int64_t n_out = total / n_in;
     const int64_t W = global ? 0 : W_of(ks);
-    const bool vec = (I[0] % 4 == 0) && fcs_aligned(out, 16);
-    const int64_t unit = vec ? 4 * DC_T : DC_T;
+    const int64_t threads = (!global && D <= 4) ? DC_T_SMALL : DC_T;
+    const int64_t unit = vec ? 4 * threads : threads;
     int64_t target = global ? 16384 : std::max<int64_t>(8192, 4 * D * W);
     target = (target + unit - 1) / unit * unit;
     const int64_t chunk = std::min(n_in, target);
@@ -275,13 +284,13 @@ extern "C" fcs_status fcs_decompress(fcs_plan_t p, const float *y, const int32_t
     const uint32_t grid = (uint32_t)(n_out * chunks);
     const size_t lds = global ? 0 : (size_t)(D * W) * sizeof(float);
     hipStream_t s = (hipStream_t)stream;
-    if (D == 1) launch_d<1>(a, vec, global, grid, lds, s);
-    else if (D == 2) launch_d<2>(a, vec, global, grid, lds, s);
-    else if (D == 3) launch_d<3>(a, vec, global, grid, lds, s);
-    else if (D <= 4) launch_d<4>(a, vec, global, grid, lds, s);
-    else if (D <= 8) launch_d<8>(a, vec, global, grid, lds, s);
-    else if (D <= 16) launch_d<16>(a, vec, global, grid, lds, s);
-    else launch_d<32>(a, vec, global, grid, lds, s);
+    if (D == 1) launch_d<1>(a, global, vec, grid, lds, s);
+    else if (D == 2) launch_d<2>(a, global, vec, grid, lds, s);
+    else if (D == 3) launch_d<3>(a, global, vec, grid, lds, s);
+    else if (D <= 4) launch_d<4>(a, global, vec, grid, lds, s);
+    else if (D <= 8) launch_d<8>(a, global, vec, grid, lds, s);
+    else if (D <= 16) launch_d<16>(a, global, vec, grid, lds, s);
+    else launch_d<32>(a, global, vec, grid, lds, s);
     FCS_LAUNCH_CHECK();
     return FCS_OK;
 }

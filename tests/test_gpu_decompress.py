@@ -43,6 +43,8 @@ def _expected(Y, hs, ss, I, order):
     ((16, 6, 5), (2048, 64, 64), 3, (1, 0, 2), 10),   # row shorter than its windows
     ((64, 1100, 3, 2), (32, 32, 16, 8), 3, None, 11),     # 6 rows over two outer modes
     ((64, 1100, 3, 2), (4096, 4096, 16, 8), 20, None, 12),  # the same, reads in place
+    ((8, 5, 7), (20000, 16, 16), 5, None, 13),            # one window exceeds LDS: reads in place
+    ((8, 1100, 3, 2), (2048, 8192, 16, 8), 4, None, 14),  # short rows: reads in place
 ])
 def test_decompress_matches_oracle(I, J, D, order, seed):
     print(f"decompress I={I} J={J} D={D} order={order}", flush=True)
