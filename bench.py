@@ -445,6 +445,45 @@ def rtpm_workload(args, torch, dev):
             "eigenvalues": [round(float(x), 5) for x in lam]}
 
 
+def rtpm50_workload(args, torch, dev):
+    """Sketched RTPM in the setting of the paper's HCS-versus-FCS table: a
+    symmetric 50^3 tensor of CP rank 10 (orthonormal basis, unit weights)
+    plus Gaussian noise at level 0.01 (relative, as for the 100^3 case),
+    J_n in {200, 300, 400} and D in {10, 20}, 15 starts and 20 iterations
+    per component.  Each cell is timed (sketch plus decomposition) and
+    reports the relative residual ||T - sum lam u o u o u|| / ||T||."""
+    import synth
+    from paper_2106_13062_amd import Plan
+    from paper_2106_13062_amd.rtpm import rtpm
+    I, R, L, iters, sigma = 50, 10, 15, 20, 0.01
+    Tv, A = synth.symmetric_cp_tensor(synth.DATA_SEED["rtpm50"], I, np.ones(R), sigma * np.sqrt(R) / I ** 1.5)
+    starts = torch.from_numpy(synth.rtpm_starts(synth.DATA_SEED["rtpm50"], R, L, I, stream=7)).to(dev)
+    T = torch.from_numpy(Tv.astype(np.float32)).to(dev)
+    Td = T.double()
+    cells = []
+    for D in (10, 20):
+        for J in (200, 300, 400):
+            plan = Plan((I, I, I), (J, J, J), D, synth.HASH_SEED["rtpm50"], device=dev)
+
+            def run():
+                y = plan.sketch_dense(T)
+                return rtpm(plan, y, starts, iters)
+
+            run()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            lam, U = run()
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3
+            Ud = U.double()
+            approx = torch.einsum("r,ir,jr,kr->kji", lam.to(dev), Ud.T, Ud.T, Ud.T).reshape(-1)
+            resid = (torch.linalg.vector_norm(Td - approx) / torch.linalg.vector_norm(Td)).item()
+            cells.append({"D": D, "J": J, "ms": ms, "residual": resid})
+            plan.close()
+    return {"workload": "rtpm50: symmetric 50^3 CP rank 10 + noise of norm 0.01 ||T||, 15 starts, 20 iterations",
+            "cells": cells}
+
+
 def als_workload(args, torch, dev):
     """Sketched alternating least squares (Section 5, ALS) in the setting of
     the paper's synthetic experiment: an asymmetric 400^3 tensor of CP rank
@@ -661,7 +700,8 @@ def main():
         print(json.dumps({"serve": serve_workload(args, torch, dev)}), flush=True)
         return
     if args.mode == "rtpm":
-        print(json.dumps({"rtpm": rtpm_workload(args, torch, dev)}), flush=True)
+        print(json.dumps({"rtpm": rtpm_workload(args, torch, dev),
+                          "rtpm50": rtpm50_workload(args, torch, dev)}), flush=True)
         return
     if args.mode == "als":
         print(json.dumps({"als": als_workload(args, torch, dev)}), flush=True)
@@ -694,6 +734,7 @@ def main():
         secondary["serve"] = serve_workload(args, torch, dev)
         log("secondary: sketched RTPM")
         secondary["rtpm"] = rtpm_workload(args, torch, dev)
+        secondary["rtpm50"] = rtpm50_workload(args, torch, dev)
         log("secondary: sketched ALS")
         secondary["als"] = als_workload(args, torch, dev)
         torch.cuda.empty_cache()

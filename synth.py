@@ -33,10 +33,10 @@ _WORKERS = max(1, min(16, os.cpu_count() or 1))
 
 DATA_SEED = {"cp100": 1001, "dense1024": 1002, "cp10k": 1003, "batch4096": 1004,
              "serve": 1005, "rtpm100": 1006,
-             "als400": 1007}
+             "als400": 1007, "rtpm50": 1008}
 HASH_SEED = {"cp100": 2001, "dense1024": 2002, "cp10k": 2003, "batch4096": 2004,
              "serve": 2005, "rtpm100": 2006,
-             "als400": 2007}
+             "als400": 2007, "rtpm50": 2008}
 
 
 def rng(seed: int, *stream: int) -> np.random.Generator:
