@@ -665,7 +665,7 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=1 << 19,
                     help="rows of the tensor the CPU oracle sketches")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "dense1024_traffic.json"))
-    ap.add_argument("--mode", default="full", choices=["full", "dense", "cp", "batch", "serve", "rtpm", "als", "decompress", "copy"],
+    ap.add_argument("--mode", default="full", choices=["full", "dense", "coo", "cp", "batch", "serve", "rtpm", "als", "decompress", "copy"],
                     help="full: headline + secondary workloads; dense: headline only; cp: the CP "
                          "sketches and T(I,u,v) only; batch: the uneven batch only; serve: the "
                          "serving loop only; copy: plain copy kernel for counter calibration")
@@ -705,6 +705,12 @@ def main():
         return
     if args.mode == "als":
         print(json.dumps({"als": als_workload(args, torch, dev)}), flush=True)
+        return
+    if args.mode == "coo":
+        import synth
+        cfg = synth.DENSE1024
+        T = synth.dense_tensor(cfg.data_seed, cfg.I)
+        print(json.dumps({"coo": coo_workload(args, torch, dev, T)}), flush=True)
         return
     if args.mode == "decompress":
         print(json.dumps({"decompress": decompress_workload(args, torch, dev)}), flush=True)

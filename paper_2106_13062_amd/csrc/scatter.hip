@@ -639,10 +639,15 @@ void launch_dense(const DenseArgs &a, bool vec4, size_t lds, unsigned grid, hipS
 
 // ---------------------------------------------------------------------------
 // COO kernel.  Each workgroup holds the hash tables of DG sketches and their
-// full J~ bins in LDS and streams a contiguous range of entries.  Bins are
-// 64-bit fixed-point integers (ds_add_u64): entries are rounded to 32-bit
-// integers at a per-workgroup power-of-two scale, so 2^31 additions cannot
-// overflow a bin and no period flush is needed; entries beyond the 32-bit
+// full J~ bins in LDS and streams a contiguous range of entries.  Entries are
+// rounded to 32-bit integers at a per-workgroup power-of-two scale and added
+// to 32-bit two's-complement bins with returning LDS atomics.  The returned
+// old value shows exactly when an addition wraps a bin past the signed
+// range: the bin's true sum then differs from its 32-bit value by one more
+// +-2^32, which is added to the sketch at once as a float (rare: a bin
+// collects a few hundred entries of magnitude below 2^28 per workgroup).
+// The hash words of the group's sketches are interleaved per index, so one
+// LDS read serves every sketch of the group.  Entries beyond the 32-bit
 // range, NaN and Inf take the float-atomic path.
 // ---------------------------------------------------------------------------
 constexpr int COO_THREADS = 1024;
@@ -663,11 +668,32 @@ struct CooArgs {
     int N, D, ngroups;
 };
 
+// hash words of the DG sketches of index row `r` of the interleaved table
+template <int DG>
+__device__ __forceinline__ void coo_words(const uint32_t *tabs, int r, uint32_t (&w)[DG]) {
+    if constexpr (DG == 2) {
+        const uint2 v = *reinterpret_cast<const uint2 *>(tabs + 2 * r);
+        w[0] = v.x;
+        w[1] = v.y;
+    } else if constexpr (DG == 4) {
+        const uint4 v = *reinterpret_cast<const uint4 *>(tabs + 4 * r);
+        w[0] = v.x;
+        w[1] = v.y;
+        w[2] = v.z;
+        w[3] = v.w;
+    } else {
+#pragma unroll
+        for (int d = 0; d < DG; ++d) w[d] = tabs[DG * r + d];
+    }
+}
+
 template <int DG>
 __global__ __launch_bounds__(COO_THREADS) void coo_scatter_kernel(CooArgs a) {
-    extern __shared__ unsigned long long smem64[];
-    unsigned long long *bins = smem64;                                        // DG x Jt
-    uint32_t *tabs = reinterpret_cast<uint32_t *>(smem64 + (size_t)DG * a.Jt);  // DG x sumI
+    extern __shared__ uint32_t smem32[];
+    const int sumI = (int)a.sumI;
+    const int Jt = (int)a.Jt;
+    uint32_t *bins = smem32;                                        // DG x Jt
+    uint32_t *tabs = smem32 + (((size_t)DG * Jt + 3) & ~(size_t)3);  // sumI x DG, 16-byte aligned
     __shared__ float wave_max[COO_THREADS / 64];
     const int64_t span = (int64_t)NXCD * a.ngroups;
     const int64_t super = blockIdx.x / span;
@@ -677,13 +703,11 @@ __global__ __launch_bounds__(COO_THREADS) void coo_scatter_kernel(CooArgs a) {
     if (chunk >= a.nchunks) return;
     const int d0 = grp * DG;
     const int nd = min(DG, a.D - d0);
-    const int sumI = (int)a.sumI;
-    const int Jt = (int)a.Jt;
     for (int k = threadIdx.x; k < DG * sumI; k += COO_THREADS) {
-        const int d = k / sumI;
-        tabs[k] = d < nd ? a.tab[(int64_t)(d0 + d) * a.sumI + (k - d * sumI)] : 0u;
+        const int i = k / DG, d = k - i * DG;
+        tabs[k] = d < nd ? a.tab[(int64_t)(d0 + d) * a.sumI + i] : 0u;
     }
-    for (int k = threadIdx.x; k < DG * Jt; k += COO_THREADS) bins[k] = 0ull;
+    for (int k = threadIdx.x; k < DG * Jt; k += COO_THREADS) bins[k] = 0u;
     const int64_t k0 = chunk * a.chunk;
     const int64_t k1 = min(k0 + a.chunk, a.nnz);
     // scale from the largest magnitude among the chunk's first 16K entries
@@ -703,7 +727,8 @@ __global__ __launch_bounds__(COO_THREADS) void coo_scatter_kernel(CooArgs a) {
     if (M0 > 0.f) F = COO_TOP - __builtin_amdgcn_frexp_expf(M0);
     F = max(-100, min(100, F));
     const float scale = ldexpf(1.0f, F);
-    const float inv = ldexpf(1.0f, -F);
+    const double inv = ldexp(1.0, -F);
+    const float wrap = (float)ldexp(1.0, 32 - F);      // one wrap of a bin, in sketch units
 
     // U entries per thread per step: their coordinate and value loads are
     // all issued before any is used, so one workgroup per CU keeps enough
@@ -733,26 +758,31 @@ __global__ __launch_bounds__(COO_THREADS) void coo_scatter_kernel(CooArgs a) {
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
+                uint32_t w[DG];
+                coo_words<DG>(tabs, ix[u], w);
 #pragma unroll
                 for (int d = 0; d < DG; ++d) {
-                    const uint32_t p = tabs[d * sumI + ix[u]];
-                    H[u][d] += (int)(p & FCS_H_MASK);
-                    S[u][d] ^= p & FCS_S_BIT;
+                    H[u][d] += (int)(w[d] & FCS_H_MASK);
+                    S[u][d] ^= w[d] & FCS_S_BIT;
                 }
             }
         }
+        int q[U][DG];
+        uint32_t old[U][DG];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            if (kb + (int64_t)u * COO_THREADS >= k1) continue;
+            const bool live = kb + (int64_t)u * COO_THREADS < k1;
             const float xs = x[u] * scale;
             const bool ok = fabsf(xs) < QLIM32;
 #pragma unroll
             for (int d = 0; d < DG; ++d) {
-                if (d < nd) {
+                q[u][d] = 0;
+                old[u][d] = 0u;
+                if (live && d < nd) {
                     if (ok) {
-                        const int q = cvt_rpi(__uint_as_float(__float_as_uint(xs) ^ S[u][d]));
-                        __hip_atomic_fetch_add(&bins[d * Jt + H[u][d]], (unsigned long long)(long long)q,
-                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        q[u][d] = cvt_rpi(__uint_as_float(__float_as_uint(xs) ^ S[u][d]));
+                        old[u][d] = __hip_atomic_fetch_add(&bins[d * Jt + H[u][d]], (uint32_t)q[u][d],
+                                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                     } else {
                         unsafeAtomicAdd(a.out + (int64_t)(d0 + d) * a.Jt + H[u][d],
                                         __uint_as_float(__float_as_uint(x[u]) ^ S[u][d]));
@@ -760,13 +790,24 @@ __global__ __launch_bounds__(COO_THREADS) void coo_scatter_kernel(CooArgs a) {
                 }
             }
         }
+        // an addition that carried the bin past the signed 32-bit range
+        // (operands of one sign, result of the other) owes it +-2^32
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+#pragma unroll
+            for (int d = 0; d < DG; ++d) {
+                const uint32_t nw = old[u][d] + (uint32_t)q[u][d];
+                if ((old[u][d] ^ nw) & ((uint32_t)q[u][d] ^ nw) & 0x80000000u)
+                    unsafeAtomicAdd(a.out + (int64_t)(d0 + d) * a.Jt + H[u][d], q[u][d] > 0 ? wrap : -wrap);
+            }
+        }
     }
     __syncthreads();
     for (int k = threadIdx.x; k < nd * Jt; k += COO_THREADS) {
-        const long long q = (long long)bins[k];
-        if (q != 0) {
+        const int qv = (int)bins[k];
+        if (qv != 0) {
             const int d = k / Jt;
-            unsafeAtomicAdd(a.out + (int64_t)(d0 + d) * a.Jt + (k - d * Jt), (float)((double)q * (double)inv));
+            unsafeAtomicAdd(a.out + (int64_t)(d0 + d) * a.Jt + (k - d * Jt), (float)((double)qv * inv));
         }
     }
 }
@@ -789,8 +830,8 @@ __global__ __launch_bounds__(256) void coo_scatter_global_kernel(CooArgs a) {
 }
 
 int coo_dg(const fcs_plan *p) {
-    const size_t budget = FCS_LDS_BYTES - 1024;
-    const size_t per_d = 8 * (size_t)p->Jt + 4 * (size_t)p->sumI;
+    const size_t budget = FCS_LDS_BYTES - 1024 - 16;
+    const size_t per_d = 4 * (size_t)p->Jt + 4 * (size_t)p->sumI;
     int dg = (int)std::min<size_t>(4, budget / per_d);
     return std::min(dg, p->D);
 }
@@ -1050,7 +1091,7 @@ extern "C" fcs_status fcs_sketch_coo(fcs_plan_t p, int64_t nnz, const int32_t *i
                                                              (int64_t)2048 / a.ngroups + 1));
     a.chunk = fcs_ceil_div(nnz, nchunks);
     a.nchunks = fcs_ceil_div(nnz, a.chunk);
-    const size_t lds = (size_t)dg * (8 * (size_t)p->Jt + 4 * (size_t)p->sumI);
+    const size_t lds = ((((size_t)dg * p->Jt + 3) & ~(size_t)3) + (size_t)dg * p->sumI) * 4;
     const unsigned grid = (unsigned)(fcs_ceil_div(a.nchunks, NXCD) * NXCD * a.ngroups);
     allow_lds(coo_scatter_kernel<1>, lds);
     allow_lds(coo_scatter_kernel<2>, lds);

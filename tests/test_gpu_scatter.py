@@ -189,6 +189,24 @@ def test_coo_duplicates_and_empty():
     assert torch.count_nonzero(empty).item() == 0
 
 
+def test_coo_bins_that_wrap():
+    """Thousands of large entries on one coordinate push its 32-bit
+    fixed-point bin past the signed range many times (every 16 additions at
+    the workgroup's scale); each wrap is carried into the sketch exactly, and
+    the sums are small integers, so the result is exact."""
+    I, J, D, seed = (30, 20, 10), (16, 16, 16), 3, 34
+    plan = Plan(I, J, D, seed, device=DEV)
+    hs, ss = O.hash_tables(seed, D, I, J)
+    n_hot = 5000
+    r = np.random.default_rng(5)
+    idx = np.concatenate([np.array([[7], [3], [2]], dtype=np.int32).repeat(n_hot, axis=1),
+                          np.stack([r.integers(0, i, 3000) for i in I]).astype(np.int32)], axis=1)
+    val = np.concatenate([np.ones(n_hot), -np.ones(1000), np.full(2000, 0.5)]).astype(np.float32)
+    got = plan.sketch_coo(dev(idx), dev(val)).cpu().numpy()
+    want = O.coo(idx, val, I, hs, ss, plan.Jt)
+    assert np.array_equal(got.astype(np.float64), want)
+
+
 def test_coo_equals_dense_of_same_entries():
     I, J, D, seed = (128, 24, 10), (64, 32, 16), 4, 33
     T, idx, val = _coo(I, 0.3, 41)
