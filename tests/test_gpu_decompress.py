@@ -45,6 +45,9 @@ def _expected(Y, hs, ss, I, order):
     ((64, 1100, 3, 2), (4096, 4096, 16, 8), 20, None, 12),  # the same, reads in place
     ((8, 5, 7), (20000, 16, 16), 5, None, 13),            # one window exceeds LDS: reads in place
     ((8, 1100, 3, 2), (2048, 8192, 16, 8), 4, None, 14),  # short rows: reads in place
+    ((1000,), (64,), 3, None, 15),                        # order 1: count sketch recovery
+    ((1, 7, 1, 5), (1, 4, 1, 8), 2, (3, 0, 2, 1), 16),    # modes of size 1 and hash length 1
+    ((4, 1, 3), (1, 1, 1), 1, None, 17),                  # J~ = 1: every entry reads bin 0
 ])
 def test_decompress_matches_oracle(I, J, D, order, seed):
     print(f"decompress I={I} J={J} D={D} order={order}", flush=True)
@@ -119,6 +122,7 @@ def _colmajor(X):
     ((6, 5, 4, 7), (8, 9, 7, 10), 5, 3, 1),
     ((30, 40, 40, 30), (64, 64, 64, 64), 50, 20, 2),      # the paper's contraction shapes
     ((33, 17, 9, 21), (512, 256, 1024, 128), 7, 2, 3),   # several transform slices
+    ((5, 4, 3, 6), (16, 8, 8, 16), 300, 2, 4),            # long shared index: several chunks of l
 ])
 def test_contraction_matches_oracle(I, J, Lc, D, seed):
     print(f"contraction I={I} J={J} Lc={Lc} D={D}", flush=True)
