@@ -160,7 +160,8 @@ enum {
     FCS_OP_FREE_MODE = 4,    /* fcs_contract_free_mode with P pairs         */
     FCS_OP_SPECTRUM = 5,     /* fcs_sketch_spectrum                         */
     FCS_OP_KRON = 6,         /* fcs_sketch_kron                             */
-    FCS_OP_CONTRACTION = 7   /* fcs_sketch_contraction, R = shared length   */
+    FCS_OP_CONTRACTION = 7,  /* fcs_sketch_contraction, R = shared length   */
+    FCS_OP_FULL = 8          /* fcs_contract_full with P tuples             */
 };
 
 /* Device workspace bytes an operation needs (R: CP rank, or the shared index
@@ -225,6 +226,27 @@ FCS_API fcs_status fcs_sketch_cp(fcs_plan_t plan, int64_t R, const float *const 
 FCS_API fcs_status fcs_sketch_kron(fcs_plan_t plan, const float *A, const float *B,
                            float *out, float *spec, void *ws, size_t ws_bytes,
                            void *stream);
+
+/* Full contraction T(v_0, ..., v_{N-1}), a vector at every mode, for P
+ * vector tuples at once (Section 4.1; T(u,u,u) of the power method).  Per
+ * sketch d, est_{d,p} = <y_d, FCS_d(v_{0,p} o ... o v_{N-1,p})>, the
+ * inner-product estimate of Proposition 1 with a rank-1 tensor, evaluated
+ * from the spectra by Parseval without forming the rank-1 sketch:
+ * (1/L) times the sum over the transform of X_d conj(prod_n F(CS_n(v_n)))
+ * (float products, sums in double); out[p] = median over d (mean of the
+ * middle pair for even D).
+ *   spec   device, float2, D x fcs_plan_spec_len (fcs_sketch_cp or
+ *          fcs_sketch_spectrum of the sketched tensor)
+ *   P      number of vector tuples >= 0 (P = 0 does nothing)
+ *   vecs   host array of N device pointers, vecs[n] P x I_n row-major float
+ *   out    device, double, P medians
+ *   per_d  device, double, P x D per-sketch estimates, or NULL; when NULL,
+ *          ws of ws_bytes >= fcs_workspace_bytes(FCS_OP_FULL, 0, P) holds
+ *          them (8-byte aligned)
+ * Errors: FCS_EINVAL, FCS_ENOMEM, FCS_EUNSUPPORTED, FCS_EDEVICE. */
+FCS_API fcs_status fcs_contract_full(fcs_plan_t plan, const float *spec, int64_t P,
+                                     const float *const *vecs, double *out, double *per_d,
+                                     void *ws, size_t ws_bytes, void *stream);
 
 /* Tensor contraction compression, Section 4.3: the FCS of
  * C[i0, i1, i2, i3] = sum_l A[i0, i1, l] B[l, i2, i3] without forming C.  By

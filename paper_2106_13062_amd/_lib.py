@@ -18,7 +18,7 @@ U64 = ctypes.c_uint64
 SZ = ctypes.c_size_t
 
 FCS_OK, FCS_EINVAL, FCS_ENOMEM, FCS_EADMIT, FCS_EDEVICE, FCS_EUNSUPPORTED = range(6)
-OP_DENSE, OP_COO, OP_CP, OP_INNER, OP_FREE_MODE, OP_SPECTRUM, OP_KRON, OP_CONTRACTION = range(8)
+OP_DENSE, OP_COO, OP_CP, OP_INNER, OP_FREE_MODE, OP_SPECTRUM, OP_KRON, OP_CONTRACTION, OP_FULL = range(9)
 ITEM_CP, ITEM_KRON = 0, 1
 NCLASS = 7
 MAX_ORDER, MAX_D, MAX_FFT = 8, 64, 16384
@@ -67,6 +67,7 @@ SIGNATURES = {
     "fcs_batch_destroy": (I32, [P]),
     "fcs_contract_inner": (I32, [P, P, P, P, P, P, SZ, P]),
     "fcs_contract_free_mode": (I32, [P, P, I32, I64, ctypes.POINTER(P), P, P, SZ, P]),
+    "fcs_contract_full": (I32, [P, P, I64, ctypes.POINTER(P), P, P, P, SZ, P]),
     "fcs_status_str": (ctypes.c_char_p, [I32]),
     "fcs_last_error": (ctypes.c_char_p, []),
 }

@@ -160,6 +160,7 @@ struct FreeArgs {
     SliceArgs s;
     float *zbuf;            // [D][Pn][J_f]
     float *est;             // [Pn][I_f][D]
+    double *full;           // full contraction: [Pn][D]
 };
 
 template <int P>
@@ -223,6 +224,59 @@ __global__ __launch_bounds__(Shape<P>::T) void free_mode_kernel(FreeArgs a) {
         const float v = z[w & FCS_H_MASK];
         a.est[((int64_t)p * If + i) * a.D + d] = __uint_as_float(__float_as_uint(v) ^ (w & FCS_S_BIT));
     }
+}
+
+// Full contraction (a vector at every mode), one workgroup per (sketch d,
+// tuple p).  By Parseval, <y_d, g> with g the linear convolution of the
+// modes' count sketches is (1/L) times the sum over all L frequencies of
+// Y conj(G); the stored slices hold the frequencies Q k + q for
+// q <= floor(Q/2), and the product is conjugate-symmetric, so slice q
+// counts c_q times (1 for q = 0 and, Q even, q = Q/2, else 2) through its
+// real part.  Sums are formed in double.
+template <int P>
+__global__ __launch_bounds__(Shape<P>::T) void full_contract_kernel(FreeArgs a) {
+    extern __shared__ float2 lds[];
+    constexpr int E = Shape<P>::E;
+    constexpr int T = Shape<P>::T;
+    const int p = blockIdx.x % a.Pn;
+    const int d = blockIdx.x / a.Pn;
+    const int32_t *invd = a.inv + (int64_t)d * a.iblock;
+    double acc = 0.0;
+    for (int q = 0; q < a.s.Qh; ++q) {
+        float2 X[E];
+        const float2 *sp = a.spec + ((int64_t)d * a.s.Qh + q) * P;
+#pragma unroll
+        for (int e = 0; e < E; ++e) X[e] = sp[threadIdx.x + e * T];
+        for (int n = 0; n < a.N; ++n) {
+            const int32_t *off = invd + a.ioff[n];
+            const float *vn = a.vecs[n] + (int64_t)p * a.I[n];
+            float2 F[E];
+            if (a.I[n] <= 2 * Lds<P>::elems) {
+                float *lv = reinterpret_cast<float *>(lds);
+                stage_column<T>(lv, vn, a.I[n]);
+                __syncthreads();
+                build_cs_slice<P>(F, lv, off, off + a.J[n] + 1, off + a.J[n] + 1 + a.I[n], a.J[n], q, a.s, 1.0f);
+                __syncthreads();
+            } else {
+                build_cs_slice<P>(F, vn, off, off + a.J[n] + 1, off + a.J[n] + 1 + a.I[n], a.J[n], q, a.s, 1.0f);
+            }
+            forward_regs<P>(lds, a.s.twP, F);
+#pragma unroll
+            for (int e = 0; e < E; ++e) X[e] = cmulc(X[e], F[e]);
+        }
+        double part = 0.0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) part += (double)X[e].x;
+        acc += ((q == 0 || 2 * q == a.s.Q) ? 1.0 : 2.0) * part;
+        __syncthreads();
+    }
+    acc = fcs_block_sum_f64<T>(acc);
+    if (threadIdx.x == 0) a.full[(int64_t)p * a.D + d] = acc / (double)a.s.L;
+}
+
+__global__ __launch_bounds__(256) void median_tuples_kernel(const double *v, int64_t Pn, int D, double *out) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < Pn) out[p] = fcs_median_small(v + p * D, D);
 }
 
 template <int MAXD>
@@ -346,6 +400,13 @@ void launch_free(const FreeArgs &fa, hipStream_t s) {
     hipLaunchKernelGGL(free_mode_kernel<P>, dim3(fa.D * fa.Pn), dim3(Shape<P>::T), lds, s, fa);
 }
 
+template <int P>
+void launch_full(const FreeArgs &fa, hipStream_t s) {
+    constexpr size_t lds = Lds<P>::bytes;
+    allow_lds_cp(full_contract_kernel<P>, lds);
+    hipLaunchKernelGGL(full_contract_kernel<P>, dim3(fa.D * fa.Pn), dim3(Shape<P>::T), lds, s, fa);
+}
+
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 }  // namespace
@@ -383,6 +444,10 @@ size_t fcs_ws_contraction(const fcs_plan *p, int64_t Lc) {
 }
 
 size_t fcs_ws_spectrum(const fcs_plan *) { return 256; }
+
+size_t fcs_ws_full(const fcs_plan *p, int64_t Pn) {
+    return std::max<size_t>(256, align256((size_t)std::max<int64_t>(Pn, 0) * p->D * sizeof(double)));
+}
 
 size_t fcs_ws_free_mode(const fcs_plan *p, int64_t Pn) {
     if (Pn <= 0) return 256;
@@ -573,6 +638,53 @@ extern "C" fcs_status fcs_contract_free_mode(fcs_plan_t p, const float *spec, in
         median_rows_kernel<32><<<grid, 256, 0, s>>>(fa.est, rows, p->D, out);
     else
         median_rows_kernel<64><<<grid, 256, 0, s>>>(fa.est, rows, p->D, out);
+    FCS_LAUNCH_CHECK();
+    return FCS_OK;
+}
+
+extern "C" fcs_status fcs_contract_full(fcs_plan_t p, const float *spec, int64_t Pn, const float *const *vecs,
+                                        double *out, double *per_d, void *ws, size_t ws_bytes, void *stream) {
+    fcs_clear_error();
+    if (!p || !p->bound) FCS_FAIL(FCS_EINVAL, "plan is null or not bound");
+    if (p->P == 0) FCS_FAIL(FCS_EUNSUPPORTED, "no transform length fits this plan");
+    if (Pn < 0) FCS_FAIL(FCS_EINVAL, "P < 0");
+    if (Pn == 0) return FCS_OK;
+    for (int n = 0; n < p->N; ++n)
+        if (p->I[n] >= FCS_MAX_GATHER_INDEX) FCS_FAIL(FCS_EUNSUPPORTED, "contractions need I_n < 2^30");
+    if (Pn > INT32_MAX / std::max<int>(1, p->D)) FCS_FAIL(FCS_EUNSUPPORTED, "too many vector tuples");
+    if (!spec || !out || !vecs) FCS_FAIL(FCS_EINVAL, "null spectrum, output or vector array");
+    for (int n = 0; n < p->N; ++n)
+        if (!vecs[n]) FCS_FAIL(FCS_EINVAL, "null vector block %d", n);
+    double *buf = per_d;
+    if (!buf) {
+        const size_t need = fcs_ws_full(p, Pn);
+        if (!ws || ws_bytes < need) FCS_FAIL(FCS_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, need);
+        if (!fcs_aligned(ws, 8)) FCS_FAIL(FCS_EINVAL, "workspace not 8-byte aligned");
+        buf = (double *)ws;
+    }
+    FreeArgs fa{};
+    fa.spec = (const float2 *)spec;
+    for (int n = 0; n < p->N; ++n) {
+        fa.vecs[n] = vecs[n];
+        fa.off[n] = p->off[n];
+        fa.ioff[n] = p->ioff[n];
+        fa.I[n] = (int)p->I[n];
+        fa.J[n] = (int)p->J[n];
+    }
+    fa.tab = p->tab;
+    fa.sumI = p->sumI;
+    fa.inv = p->inv;
+    fa.iblock = p->iblock;
+    fa.N = p->N;
+    fa.D = p->D;
+    fa.Pn = (int)Pn;
+    fa.free_mode = -1;
+    fa.s = slice_args(p);
+    fa.full = buf;
+    hipStream_t s = (hipStream_t)stream;
+    FCS_DISPATCH_FFT(p->P, (launch_full<PP>(fa, s)));
+    FCS_LAUNCH_CHECK();
+    median_tuples_kernel<<<(unsigned)fcs_ceil_div(Pn, 256), 256, 0, s>>>(buf, Pn, p->D, out);
     FCS_LAUNCH_CHECK();
     return FCS_OK;
 }

@@ -120,3 +120,4 @@ size_t fcs_ws_free_mode(const fcs_plan *p, int64_t P);
 size_t fcs_ws_spectrum(const fcs_plan *p);
 size_t fcs_ws_kron(const fcs_plan *p);
 size_t fcs_ws_contraction(const fcs_plan *p, int64_t Lc);
+size_t fcs_ws_full(const fcs_plan *p, int64_t Pn);

@@ -451,6 +451,7 @@ extern "C" size_t fcs_workspace_bytes(fcs_plan_t p, int32_t op, int64_t R, int64
     case FCS_OP_SPECTRUM: return fcs_ws_spectrum(p);
     case FCS_OP_KRON: return fcs_ws_kron(p);
     case FCS_OP_CONTRACTION: return fcs_ws_contraction(p, R);
+    case FCS_OP_FULL: return fcs_ws_full(p, P);
     default: return 0;
     }
 }

@@ -258,6 +258,29 @@ class Plan:
         return out
 
 
+    def contract_full(self, spec: torch.Tensor, vecs, out=None, per_d=None, ws=None, stream=None):
+        """T(v_0, ..., v_{N-1}) for P tuples: vecs is a list of N float32
+        P x I_n tensors.  Returns (medians float64 [P], per-sketch float64
+        P x D)."""
+        _need(spec, torch.float32, "spec")
+        if len(vecs) != self.N:
+            raise ValueError("one vector block per mode")
+        ptrs = (ctypes.c_void_p * self.N)()
+        Pn = None
+        for n in range(self.N):
+            v = _need(vecs[n], torch.float32, f"vecs[{n}]")
+            if Pn is None:
+                Pn = int(v.shape[0])
+            if tuple(v.shape) != (Pn, self.I[n]):
+                raise ValueError(f"vecs[{n}] must be P x I_n")
+            ptrs[n] = v.data_ptr()
+        out = torch.empty(Pn, dtype=torch.float64, device=self.device) if out is None else out
+        per_d = torch.empty((Pn, self.D), dtype=torch.float64, device=self.device) if per_d is None else per_d
+        C.check(self.lib.fcs_contract_full(self._h, _ptr(spec), Pn, ptrs, _ptr(out), _ptr(per_d), None, 0,
+                                           _stream(stream)))
+        return out, per_d
+
+
 class Batch:
     """Many uneven CP / Kronecker sketch computations run together by the
     persistent batch kernels (include/fcs.h, fcs_batch_*).

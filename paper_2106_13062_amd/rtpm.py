@@ -7,8 +7,8 @@ For each component k:
     vectors at once: T(I,u,u) is the free-mode contraction of the sketch
     spectra (fcs_contract_free_mode, median over the D sketches);
   * the eigenvalue T(u,u,u) of every start: the median over d of
-    <FCS_d(T), FCS_d(u o u o u)> (fcs_sketch_cp of the rank-1 tensor, then
-    fcs_contract_inner);
+    <FCS_d(T), FCS_d(u o u o u)>, all L starts in one fcs_contract_full
+    launch on the (deflated) spectra;
   * the start with the largest eigenvalue is kept, and the sketch and its
     spectra are deflated by linearity:
     FCS(T - lam u o u o u) = FCS(T) - lam FCS(u o u o u).
@@ -47,12 +47,7 @@ def rtpm(plan: Plan, y: torch.Tensor, starts: torch.Tensor, iters: int, stream=N
             for _ in range(iters):
                 W = plan.contract_free_mode(spec, 0, [None, U, U], stream=s)
                 U = (W / torch.linalg.vector_norm(W, dim=1, keepdim=True)).to(torch.float32).contiguous()
-            lam = torch.empty(L, dtype=torch.float64, device=y.device)
-            for j in range(L):
-                uj = U[j:j + 1]
-                yj, _ = plan.sketch_cp([uj, uj, uj], stream=s)
-                med, _ = plan.contract_inner(y, yj, stream=s)
-                lam[j:j + 1] = med
+            lam, _ = plan.contract_full(spec, [U, U, U], stream=s)
             j = int(torch.argmax(lam).item())
             lk = float(lam[j].item())
             u = U[j:j + 1].contiguous()

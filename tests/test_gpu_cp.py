@@ -164,6 +164,32 @@ def test_free_mode_from_dense_sketch():
         assert rel(out[p], want) <= TOL
 
 
+@pytest.mark.parametrize("I,J,D,Pn,L", [
+    ((30, 20, 10), (64, 32, 16), 3, 5, 0),
+    ((50, 40, 30, 20), (128, 64, 64, 32), 4, 3, 0),      # order 4, even D
+    ((200, 150, 100), (1024, 512, 256), 5, 7, 8192),     # several transform slices
+])
+def test_full_contraction_parity(I, J, D, Pn, L):
+    """T(v_0, ..., v_{N-1}) for P tuples from the spectra (Parseval) against
+    the oracle's literal <y_d, FCS_d(v_0 o ... o v_{N-1})> and its median."""
+    print(f"full contraction I={I} J={J} D={D} P={Pn} L={L}", flush=True)
+    seed, R = 33, 4
+    U = synth.cp_factors(16, I, R)
+    plan = Plan(I, J, D, seed, L=L, device=DEV)
+    _, spec = plan.sketch_cp(dev_factors(U), want_out=False, want_spec=True)
+    vecs_np = [synth.unit_vectors(50 + n, Pn, I[n]) for n in range(len(I))]
+    med, per_d = plan.contract_full(spec, [dev(v) for v in vecs_np])
+    med, per_d = med.cpu().numpy(), per_d.cpu().numpy()
+    hs, ss = O.hash_tables(seed, D, I, J)
+    Y = np.stack([O.fcs_cp_conv(None, U, hs[d], ss[d], J) for d in range(D)])
+    for p in range(Pn):
+        vv = [vecs_np[n][p] for n in range(len(I))]
+        want_d = np.array([O.contract_full(Y[d], hs[d], ss[d], J, vv) for d in range(D)])
+        scale = max(np.linalg.norm(Y[d]) * np.linalg.norm(O.fcs_rank1(vv, hs[d], ss[d], J)) for d in range(D))
+        assert np.all(np.abs(per_d[p] - want_d) <= TOL * scale), (p, per_d[p], want_d)
+        assert abs(med[p] - O.median(want_d)) <= TOL * scale
+
+
 def test_cp_full_size_workload():
     """Order 3, I_n = 10^4, R = 512 unit-norm columns, J_n = 2^14, D = 10,
     and T(I, u, v) for 64 unit vector pairs, in the launch configuration the
