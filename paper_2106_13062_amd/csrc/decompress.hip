@@ -31,6 +31,7 @@ namespace {
 
 constexpr int DC_T = 512;                   // threads of the in-place and larger-D kernels
 constexpr int DC_T_SMALL = 1024;            // staged kernels with D <= 4
+constexpr int DC_T_PHASE = 256;             // in-place kernel with D > 4, one sketch at a time
 constexpr int64_t DC_LDS_FLOATS = 36864;    // 144 KB of staged windows
 constexpr int DC_MAXD = 32;
 constexpr int64_t DC_ROW_TARGET = 65536;    // inner entries per row worth aiming for
@@ -183,6 +184,75 @@ __global__ __launch_bounds__(T) void decompress_kernel(DecompArgs a) {
     }
 }
 
+// In-place reads for larger D, one sketch at a time: a tile is four
+// entries per thread of one row (leading output dimension a multiple of 4,
+// out 16-byte aligned).  Every thread gathers its four estimates of sketch
+// d from y_d, then the workgroup meets at a barrier before sketch d + 1, so
+// its waves read inside one sketch's row window (W floats) at a time and
+// mostly hit the CU's L1 instead of spreading over all D windows.  The D
+// estimates stay in registers until the median.
+template <int MAXD>
+__global__ __launch_bounds__(DC_T_PHASE) void decompress_phase_kernel(DecompArgs a) {
+    __shared__ uint32_t rowb[FCS_MAX_D];
+    const int t = threadIdx.x;
+    const int D = a.D;
+    const uint32_t r = blockIdx.x / a.chunks;
+    const uint32_t c0 = (blockIdx.x - r * a.chunks) * a.chunk;
+    const uint32_t e = c0 + 4 * t;
+    const bool live = e < min(c0 + a.chunk, a.n_in);
+    if (t < D) {
+        uint32_t rem = r, w = 0;
+        for (int k = a.ks; k < a.N; ++k) {
+            const uint32_t j = rem % a.n[k];
+            rem /= a.n[k];
+            w += a.tab[k][t * a.sumI + j];
+        }
+        rowb[t] = w;
+    }
+    // inner indices of the thread's first entry (a thread past the end of
+    // the row takes entry 0, whose reads are in range, and stores nothing)
+    uint32_t jk[FCS_MAX_ORDER];
+    {
+        uint32_t rem = live ? e : 0u;
+#pragma unroll
+        for (int k = 0; k < FCS_MAX_ORDER; ++k) {
+            jk[k] = 0u;
+            if (k < a.ks) {
+                jk[k] = rem % a.n[k];
+                rem /= a.n[k];
+            }
+        }
+    }
+    __syncthreads();
+    float v[4][MAXD];
+#pragma unroll
+    for (int d = 0; d < MAXD; ++d) {
+        if (d < D) {
+            uint32_t bw = rowb[d];
+#pragma unroll
+            for (int k = 1; k < FCS_MAX_ORDER; ++k)
+                if (k < a.ks) bw += a.tab[k][d * a.sumI + jk[k]];
+            const uint32_t *h0 = a.tab[0] + d * a.sumI + jk[0];
+            const float *yd = a.y + (int64_t)d * a.Jt;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint32_t w = bw + h0[q];
+                v[q][d] = __uint_as_float(__float_as_uint(yd[w & FCS_H_MASK]) ^ (w & FCS_S_BIT));
+            }
+            __syncthreads();
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v[q][d] = 0.f;
+        }
+    }
+    if (!live) return;
+    float res[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) res[q] = median_of<MAXD>(v[q], D);
+    const f32x4 o = {res[0], res[1], res[2], res[3]};
+    __builtin_nontemporal_store(o, reinterpret_cast<f32x4 *>(a.out + (int64_t)r * a.n_in + e));
+}
+
 template <int MAXD, bool VEC, bool GLOBAL, int T>
 void launch(const DecompArgs &a, uint32_t grid, size_t lds, hipStream_t s) {
     auto k = decompress_kernel<MAXD, VEC, GLOBAL, T>;
@@ -193,6 +263,12 @@ void launch(const DecompArgs &a, uint32_t grid, size_t lds, hipStream_t s) {
 template <int MAXD>
 void launch_d(const DecompArgs &a, bool global, bool vec, uint32_t grid, size_t lds, hipStream_t s) {
     constexpr int TS = MAXD <= 4 ? DC_T_SMALL : DC_T;
+    if constexpr (MAXD >= 8) {
+        if (vec && global) {
+            hipLaunchKernelGGL(decompress_phase_kernel<MAXD>, dim3(grid), dim3(DC_T_PHASE), 0, s, a);
+            return;
+        }
+    }
     if (vec) {
         if (global) launch<MAXD, true, true, DC_T>(a, grid, lds, s);
         else launch<MAXD, true, false, TS>(a, grid, lds, s);
@@ -269,9 +345,10 @@ extern "C" fcs_status fcs_decompress(fcs_plan_t p, const float *y, const int32_t
     const int64_t n_in = nin_of(ks);
     const int64_t n_out = total / n_in;
     const int64_t W = global ? 0 : W_of(ks);
-    const int64_t threads = (!global && D <= 4) ? DC_T_SMALL : DC_T;
+    const bool phase = global && vec && D > 4;      // decompress_phase_kernel
+    const int64_t threads = phase ? DC_T_PHASE : (!global && D <= 4) ? DC_T_SMALL : DC_T;
     const int64_t unit = vec ? 4 * threads : threads;
-    int64_t target = global ? 16384 : std::max<int64_t>(8192, 4 * D * W);
+    int64_t target = phase ? unit : global ? 16384 : std::max<int64_t>(8192, 4 * D * W);
     target = (target + unit - 1) / unit * unit;
     const int64_t chunk = std::min(n_in, target);
     const int64_t chunks = fcs_ceil_div(n_in, chunk);
