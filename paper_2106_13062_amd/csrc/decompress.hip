@@ -93,6 +93,43 @@ __device__ __forceinline__ float median_of(float (&v)[MAXD], int D) {
     }
 }
 
+// Batcher's odd-even merge sort over slots [0, DN) of an NP-slot network
+// (NP the power of two >= DN), all comparators ascending.  Slots at and
+// above DN would hold +inf, so a comparator that reaches one of them moves
+// nothing; it is left out at compile time (103 comparators for DN = 20
+// against 240 for the bitonic network over 32 slots).
+template <int NP, int DN>
+__device__ __forceinline__ void sort_exact(float (&v)[DN]) {
+#pragma unroll
+    for (int p = 1; p < NP; p <<= 1) {
+#pragma unroll
+        for (int k = p; k >= 1; k >>= 1) {
+#pragma unroll
+            for (int j = k % p; j + k < NP; j += 2 * k) {
+#pragma unroll
+                for (int i = 0; i < k; ++i) {
+                    const int a = i + j, b = i + j + k;
+                    if (b < DN && a / (2 * p) == b / (2 * p)) {
+                        const float x = v[a], y = v[b];
+                        v[a] = fminf(x, y);
+                        v[b] = fmaxf(x, y);
+                    }
+                }
+            }
+        }
+    }
+}
+
+template <int DN>
+__device__ __forceinline__ float median_exact(float (&v)[DN]) {
+    constexpr int NP = DN <= 8 ? 8 : DN <= 16 ? 16 : 32;
+    sort_exact<NP, DN>(v);
+    if constexpr (DN & 1)
+        return v[(DN - 1) / 2];
+    else
+        return (float)(0.5 * ((double)v[DN / 2 - 1] + (double)v[DN / 2]));
+}
+
 // Estimate of sketch d for an entry whose summed hash word is `word`
 // (inner part only when the window is staged, the whole sum otherwise).
 template <bool GLOBAL>
@@ -190,12 +227,12 @@ __global__ __launch_bounds__(T) void decompress_kernel(DecompArgs a) {
 // d from y_d, then the workgroup meets at a barrier before sketch d + 1, so
 // its waves read inside one sketch's row window (W floats) at a time and
 // mostly hit the CU's L1 instead of spreading over all D windows.  The D
-// estimates stay in registers until the median.
-template <int MAXD>
+// estimates stay in registers until the median, which a sorting network
+// for exactly D values forms (one instance per D).
+template <int D>
 __global__ __launch_bounds__(DC_T_PHASE) void decompress_phase_kernel(DecompArgs a) {
     __shared__ uint32_t rowb[FCS_MAX_D];
     const int t = threadIdx.x;
-    const int D = a.D;
     const uint32_t r = blockIdx.x / a.chunks;
     const uint32_t c0 = (blockIdx.x - r * a.chunks) * a.chunk;
     const uint32_t e = c0 + 4 * t;
@@ -224,31 +261,26 @@ __global__ __launch_bounds__(DC_T_PHASE) void decompress_phase_kernel(DecompArgs
         }
     }
     __syncthreads();
-    float v[4][MAXD];
+    float v[4][D];
 #pragma unroll
-    for (int d = 0; d < MAXD; ++d) {
-        if (d < D) {
-            uint32_t bw = rowb[d];
+    for (int d = 0; d < D; ++d) {
+        uint32_t bw = rowb[d];
 #pragma unroll
-            for (int k = 1; k < FCS_MAX_ORDER; ++k)
-                if (k < a.ks) bw += a.tab[k][d * a.sumI + jk[k]];
-            const uint32_t *h0 = a.tab[0] + d * a.sumI + jk[0];
-            const float *yd = a.y + (int64_t)d * a.Jt;
+        for (int k = 1; k < FCS_MAX_ORDER; ++k)
+            if (k < a.ks) bw += a.tab[k][d * a.sumI + jk[k]];
+        const uint32_t *h0 = a.tab[0] + d * a.sumI + jk[0];
+        const float *yd = a.y + (int64_t)d * a.Jt;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const uint32_t w = bw + h0[q];
-                v[q][d] = __uint_as_float(__float_as_uint(yd[w & FCS_H_MASK]) ^ (w & FCS_S_BIT));
-            }
-            __syncthreads();
-        } else {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) v[q][d] = 0.f;
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t w = bw + h0[q];
+            v[q][d] = __uint_as_float(__float_as_uint(yd[w & FCS_H_MASK]) ^ (w & FCS_S_BIT));
         }
+        __syncthreads();
     }
     if (!live) return;
     float res[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) res[q] = median_of<MAXD>(v[q], D);
+    for (int q = 0; q < 4; ++q) res[q] = median_exact<D>(v[q]);
     const f32x4 o = {res[0], res[1], res[2], res[3]};
     __builtin_nontemporal_store(o, reinterpret_cast<f32x4 *>(a.out + (int64_t)r * a.n_in + e));
 }
@@ -260,12 +292,24 @@ void launch(const DecompArgs &a, uint32_t grid, size_t lds, hipStream_t s) {
     hipLaunchKernelGGL(k, dim3(grid), dim3(T), lds, s, a);
 }
 
+// the in-place kernel instance of the plan's D (5 .. DC_MAXD)
+template <int DN>
+void launch_phase(const DecompArgs &a, uint32_t grid, hipStream_t s) {
+    if constexpr (DN <= DC_MAXD) {
+        if (a.D == DN) {
+            hipLaunchKernelGGL(decompress_phase_kernel<DN>, dim3(grid), dim3(DC_T_PHASE), 0, s, a);
+            return;
+        }
+        launch_phase<DN + 1>(a, grid, s);
+    }
+}
+
 template <int MAXD>
 void launch_d(const DecompArgs &a, bool global, bool vec, uint32_t grid, size_t lds, hipStream_t s) {
     constexpr int TS = MAXD <= 4 ? DC_T_SMALL : DC_T;
     if constexpr (MAXD >= 8) {
         if (vec && global) {
-            hipLaunchKernelGGL(decompress_phase_kernel<MAXD>, dim3(grid), dim3(DC_T_PHASE), 0, s, a);
+            launch_phase<5>(a, grid, s);
             return;
         }
     }
