@@ -51,6 +51,9 @@ Parity status of each function (what pins it is in ``tests/test_oracle_*.py``):
 * ``rtpm``               pinned by recovering the planted components and
                           weights of an orthogonally decomposable symmetric
                           tensor (the setting of the RTPM experiments).
+* ``rtpm_asym``          pinned by recovering the planted components and
+                          weights of an asymmetric tensor with orthonormal
+                          factors.
 * ``als``                pinned by recovering the planted factors and
                           weights of an asymmetric tensor with orthonormal
                           factors (the setting of the ALS experiment), and by
@@ -446,6 +449,41 @@ def rtpm(Y, hs, ss, J, rank: int, inits, iters: int):
             Y[d] -= lam[j] * fcs_rank1([u, u, u], hs[d], ss[d], J)
     return np.array(lams), np.stack(comps)
 
+
+
+def rtpm_asym(Y, hs, ss, J, rank: int, inits, iters: int):
+    """RTPM for an asymmetric order-3 tensor (Section 5: the power iteration
+    becomes an alternating rank-1 update).  Y: D x J~ sketches; inits:
+    rank x L x 3 x I_max starting vectors (mode n uses the first I_n
+    entries of slot n).  Per component and start: u <- T(I,v,w), then
+    v <- T(u,I,w), then w <- T(u,v,I), each normalised, ``iters`` times; the
+    eigenvalue T(u,v,w); the start with the largest eigenvalue is kept and
+    deflated from the sketches.  Returns (eigenvalues [rank], [U, V, W] with
+    the components as rows)."""
+    Y = np.array(Y, dtype=np.float64)
+    D = Y.shape[0]
+    Is = [len(hs[0][n]) for n in range(3)]
+    lams, comps = [], [[], [], []]
+    for k in range(rank):
+        best = None
+        for start in inits[k]:
+            x = [np.array(start[n][:Is[n]], dtype=np.float64) for n in range(3)]
+            x = [v / np.linalg.norm(v) for v in x]
+            for _ in range(iters):
+                for n in range(3):
+                    o = [m for m in range(3) if m != n]
+                    g = contract_free_median(Y, hs, ss, J, n, [x[m] for m in o])
+                    x[n] = g / np.linalg.norm(g)
+            lam = median([contract_full(Y[d], hs[d], ss[d], J, x) for d in range(D)])
+            if best is None or lam > best[0]:
+                best = (lam, x)
+        lam, x = best
+        lams.append(float(lam))
+        for n in range(3):
+            comps[n].append(x[n])
+        for d in range(D):
+            Y[d] -= lam * fcs_rank1(x, hs[d], ss[d], J)
+    return np.array(lams), [np.stack(c) for c in comps]
 
 
 # ---------------------------------------------------------------------------

@@ -33,10 +33,10 @@ _WORKERS = max(1, min(16, os.cpu_count() or 1))
 
 DATA_SEED = {"cp100": 1001, "dense1024": 1002, "cp10k": 1003, "batch4096": 1004,
              "serve": 1005, "rtpm100": 1006,
-             "als400": 1007, "rtpm50": 1008}
+             "als400": 1007, "rtpm50": 1008, "rtpm_asym100": 1009}
 HASH_SEED = {"cp100": 2001, "dense1024": 2002, "cp10k": 2003, "batch4096": 2004,
              "serve": 2005, "rtpm100": 2006,
-             "als400": 2007, "rtpm50": 2008}
+             "als400": 2007, "rtpm50": 2008, "rtpm_asym100": 2009}
 
 
 def rng(seed: int, *stream: int) -> np.random.Generator:
@@ -170,6 +170,12 @@ def als_init(seed: int, size: int, rank: int, stream: int = 0):
     """Three float32 size x rank starting factors of ALS, N(0, 1) entries."""
     g = rng(seed, stream)
     return [g.standard_normal((int(size), int(rank))).astype(np.float32) for _ in range(3)]
+
+
+def rtpm_asym_starts(seed: int, rank: int, count: int, size: int, stream: int = 0) -> np.ndarray:
+    """rank x count x 3 x size float32 unit starting vectors of the
+    alternating rank-1 updates (one triple per start)."""
+    return unit_vectors(seed, rank * count * 3, size, stream).reshape(int(rank), int(count), 3, int(size))
 
 
 def rtpm_starts(seed: int, rank: int, count: int, size: int, stream: int = 0) -> np.ndarray:
