@@ -58,3 +58,50 @@ def rtpm(plan: Plan, y: torch.Tensor, starts: torch.Tensor, iters: int, stream=N
             y -= yk
             spec -= sk
     return torch.tensor(lams, dtype=torch.float64), comps
+
+
+def rtpm_asym(plan: Plan, y: torch.Tensor, starts: torch.Tensor, iters: int, stream=None):
+    """RTPM for an asymmetric order-3 tensor: the power iteration becomes an
+    alternating rank-1 update, u <- T(I,v,w), v <- T(u,I,w), w <- T(u,v,I),
+    each normalised (one batched free-mode contraction per mode and
+    iteration, all L starts at once); the eigenvalue T(u,v,w) of every
+    start from one full contraction; the best start is deflated from the
+    sketch and its spectra by linearity.
+    plan: bound Plan of an order-3 shape; y: float32 D x J~ sketch (not
+    modified); starts: float32 rank x L x 3 x max(I_n) starting vectors
+    (mode n uses the first I_n entries of slot n).  Returns (eigenvalues
+    float64 [rank] on the host, three float32 rank x I_n component
+    matrices on the device)."""
+    if plan.N != 3:
+        raise ValueError("RTPM needs a plan of an order-3 shape")
+    rank, L, three, Imax = (int(x) for x in starts.shape)
+    if three != 3 or Imax < max(plan.I):
+        raise ValueError("starting vectors must be rank x L x 3 x max(I_n)")
+    s = torch.cuda.current_stream() if stream is None else stream
+    with torch.cuda.stream(s):
+        y = y.clone()
+        spec = plan.spectrum(y, stream=s)
+        lams = []
+        comps = [torch.empty((rank, plan.I[n]), dtype=torch.float32, device=y.device) for n in range(3)]
+        for k in range(rank):
+            X = []
+            for n in range(3):
+                v = starts[k, :, n, :plan.I[n]].to(torch.float32)
+                X.append((v / torch.linalg.vector_norm(v, dim=1, keepdim=True)).contiguous())
+            for _ in range(iters):
+                for n in range(3):
+                    vecs = [None if m == n else X[m] for m in range(3)]
+                    G = plan.contract_free_mode(spec, n, vecs, stream=s)
+                    X[n] = (G / torch.linalg.vector_norm(G, dim=1, keepdim=True)).to(torch.float32).contiguous()
+            lam, _ = plan.contract_full(spec, X, stream=s)
+            j = int(torch.argmax(lam).item())
+            lk = float(lam[j].item())
+            lams.append(lk)
+            x = [X[n][j:j + 1].contiguous() for n in range(3)]
+            for n in range(3):
+                comps[n][k] = x[n][0]
+            lt = torch.tensor([lk], dtype=torch.float32, device=y.device)
+            yk, sk = plan.sketch_cp(x, lam=lt, want_spec=True, stream=s)
+            y -= yk
+            spec -= sk
+    return torch.tensor(lams, dtype=torch.float64), comps

@@ -38,3 +38,30 @@ def test_rtpm_matches_oracle(I, J, D, w, noise, L, iters):
     assert np.all(1.0 - agree <= 1e-4), agree
     # and both found the planted basis in weight order
     assert list(np.abs(U_g @ A).argmax(axis=1)) == list(range(R))
+
+
+@pytest.mark.parametrize("I,J,D,w,noise,L,iters", [
+    (20, 2048, 3, (3.0, 2.0, 1.0), 0.0, 4, 10),
+    (24, 2048, 2, (4.0, 3.0, 2.0, 1.0), 0.01, 3, 8),
+])
+def test_asymmetric_rtpm_matches_oracle(I, J, D, w, noise, L, iters):
+    from paper_2106_13062_amd.rtpm import rtpm_asym
+    print(f"asymmetric rtpm I={I} J={J} D={D} R={len(w)}", flush=True)
+    R = len(w)
+    Tv, F = synth.asymmetric_cp_tensor(14, I, w, noise)
+    starts = synth.rtpm_asym_starts(34, R, L, I)
+    plan = Plan((I, I, I), (J, J, J), D, 24, device=DEV)
+    y = plan.sketch_dense(torch.from_numpy(Tv.astype(np.float32)).to(DEV))
+    lam_g, X_g = rtpm_asym(plan, y, torch.from_numpy(starts).to(DEV), iters)
+    torch.cuda.synchronize()
+    lam_g = lam_g.numpy()
+    X_g = [x.cpu().numpy().astype(np.float64) for x in X_g]
+    hs, ss = O.hash_tables(24, D, (I, I, I), (J, J, J))
+    T = Tv.astype(np.float32).astype(np.float64).reshape((I, I, I), order="F")
+    Y = np.stack([O.fcs_dense(T, hs[d], ss[d], (J, J, J)) for d in range(D)])
+    lam_o, X_o = O.rtpm_asym(Y, hs, ss, (J, J, J), R, starts, iters)
+    assert np.all(np.abs(lam_g - lam_o) <= 1e-4 * np.abs(lam_o)), (lam_g, lam_o)
+    for n in range(3):
+        agree = np.abs(np.sum(X_g[n] * X_o[n], axis=1)) / np.linalg.norm(X_g[n], axis=1)
+        assert np.all(1.0 - agree <= 1e-4), (n, agree)
+        assert list(np.abs(X_g[n] @ F[n]).argmax(axis=1)) == list(range(R))
