@@ -731,9 +731,11 @@ __global__ __launch_bounds__(COO_THREADS) void coo_scatter_kernel(CooArgs a) {
     const float wrap = (float)ldexp(1.0, 32 - F);      // one wrap of a bin, in sketch units
 
     // U entries per thread per step: their coordinate and value loads are
-    // all issued before any is used, so one workgroup per CU keeps enough
-    // loads in flight
-    constexpr int U = 8;
+    // all issued before any is used, and their returning atomics before any
+    // result is checked, so one workgroup per CU keeps enough of both in
+    // flight (16 against 8: 1.19 against 1.29 ms on 1.07e8 entries, D = 8;
+    // 32 spills)
+    constexpr int U = 16;
     for (int64_t kb = k0 + threadIdx.x; kb < k1; kb += (int64_t)COO_THREADS * U) {
         float x[U];
         int H[U][DG];
