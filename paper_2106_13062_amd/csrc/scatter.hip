@@ -734,60 +734,60 @@ __global__ __launch_bounds__(COO_THREADS) void coo_scatter_kernel(CooArgs a) {
     // all issued before any is used, and their returning atomics before any
     // result is checked, so one workgroup per CU keeps enough of both in
     // flight (16 against 8: 1.19 against 1.29 ms on 1.07e8 entries, D = 8;
-    // 32 spills)
-    constexpr int U = 16;
-    for (int64_t kb = k0 + threadIdx.x; kb < k1; kb += (int64_t)COO_THREADS * U) {
+    // 32 spills, and so do 16 with more than two sketches per group)
+    constexpr int U = DG <= 2 ? 16 : 8;
+    // entries of the chunk are indexed in 32 bits from its start, and the
+    // hash words of the modes are added as packed words: their hash parts
+    // sum below J~ < 2^31, so bit 31 of the sum is the sign of the product
+    const int nloc = (int)(k1 - k0);
+    const float *vals = a.val + k0;
+    for (int kb = threadIdx.x; kb < nloc; kb += COO_THREADS * U) {
         float x[U];
-        int H[U][DG];
-        uint32_t S[U][DG];
+        uint32_t Wd[U][DG];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int64_t k = kb + (int64_t)u * COO_THREADS;
-            x[u] = k < k1 ? a.val[k] : 0.f;
+            const int k = kb + u * COO_THREADS;
+            x[u] = k < nloc ? vals[k] : 0.f;
 #pragma unroll
-            for (int d = 0; d < DG; ++d) {
-                H[u][d] = 0;
-                S[u][d] = 0;
-            }
+            for (int d = 0; d < DG; ++d) Wd[u][d] = 0u;
         }
         for (int n = 0; n < a.N; ++n) {
-            const int32_t *col = a.idx + (int64_t)n * a.nnz;
+            const int32_t *col = a.idx + (int64_t)n * a.nnz + k0;
             int ix[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const int64_t k = kb + (int64_t)u * COO_THREADS;
-                ix[u] = (k < k1 ? col[k] : 0) + (int)a.off[n];
+                const int k = kb + u * COO_THREADS;
+                ix[u] = (k < nloc ? col[k] : 0) + (int)a.off[n];
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 uint32_t w[DG];
                 coo_words<DG>(tabs, ix[u], w);
 #pragma unroll
-                for (int d = 0; d < DG; ++d) {
-                    H[u][d] += (int)(w[d] & FCS_H_MASK);
-                    S[u][d] ^= w[d] & FCS_S_BIT;
-                }
+                for (int d = 0; d < DG; ++d) Wd[u][d] += w[d];
             }
         }
         int q[U][DG];
         uint32_t old[U][DG];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const bool live = kb + (int64_t)u * COO_THREADS < k1;
+            const bool live = kb + u * COO_THREADS < nloc;
             const float xs = x[u] * scale;
             const bool ok = fabsf(xs) < QLIM32;
 #pragma unroll
             for (int d = 0; d < DG; ++d) {
+                const int H = (int)(Wd[u][d] & FCS_H_MASK);
+                const uint32_t S = Wd[u][d] & FCS_S_BIT;
                 q[u][d] = 0;
                 old[u][d] = 0u;
                 if (live && d < nd) {
                     if (ok) {
-                        q[u][d] = cvt_rpi(__uint_as_float(__float_as_uint(xs) ^ S[u][d]));
-                        old[u][d] = __hip_atomic_fetch_add(&bins[d * Jt + H[u][d]], (uint32_t)q[u][d],
+                        q[u][d] = cvt_rpi(__uint_as_float(__float_as_uint(xs) ^ S));
+                        old[u][d] = __hip_atomic_fetch_add(&bins[d * Jt + H], (uint32_t)q[u][d],
                                                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                     } else {
-                        unsafeAtomicAdd(a.out + (int64_t)(d0 + d) * a.Jt + H[u][d],
-                                        __uint_as_float(__float_as_uint(x[u]) ^ S[u][d]));
+                        unsafeAtomicAdd(a.out + (int64_t)(d0 + d) * a.Jt + H,
+                                        __uint_as_float(__float_as_uint(x[u]) ^ S));
                     }
                 }
             }
@@ -800,7 +800,8 @@ __global__ __launch_bounds__(COO_THREADS) void coo_scatter_kernel(CooArgs a) {
             for (int d = 0; d < DG; ++d) {
                 const uint32_t nw = old[u][d] + (uint32_t)q[u][d];
                 if ((old[u][d] ^ nw) & ((uint32_t)q[u][d] ^ nw) & 0x80000000u)
-                    unsafeAtomicAdd(a.out + (int64_t)(d0 + d) * a.Jt + H[u][d], q[u][d] > 0 ? wrap : -wrap);
+                    unsafeAtomicAdd(a.out + (int64_t)(d0 + d) * a.Jt + (int)(Wd[u][d] & FCS_H_MASK),
+                                    q[u][d] > 0 ? wrap : -wrap);
             }
         }
     }
@@ -1091,6 +1092,8 @@ extern "C" fcs_status fcs_sketch_coo(fcs_plan_t p, int64_t nnz, const int32_t *i
     // chunks: each workgroup streams many more entries than it has bins
     int64_t nchunks = std::max<int64_t>(1, std::min<int64_t>(nnz / std::max<int64_t>(1, 8 * p->Jt),
                                                              (int64_t)2048 / a.ngroups + 1));
+    // the kernel indexes a chunk's entries in 32 bits
+    nchunks = std::max<int64_t>(nchunks, fcs_ceil_div(nnz, (int64_t)1 << 30));
     a.chunk = fcs_ceil_div(nnz, nchunks);
     a.nchunks = fcs_ceil_div(nnz, a.chunk);
     const size_t lds = ((((size_t)dg * p->Jt + 3) & ~(size_t)3) + (size_t)dg * p->sumI) * 4;
