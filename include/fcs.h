@@ -172,8 +172,21 @@ FCS_API size_t fcs_workspace_bytes(fcs_plan_t plan, int32_t op, int64_t R, int64
  * pass over T.
  *   T    device, float, prod_n I_n entries in vec order (mode 0 fastest)
  *   out  device, float, D x J~ row-major; overwritten
- *   ws   device workspace of ws_bytes >= fcs_workspace_bytes(FCS_OP_DENSE)
- * Float sums are accumulated in a scheduling-dependent order, so results may
+ *   ws   device workspace of ws_bytes >= fcs_workspace_bytes(FCS_OP_DENSE),
+ *        4-byte aligned.  On return (stream order) its first two 32-bit
+ *        words count the row blocks that were redone in the exact pass
+ *        (first launch pass: full groups of sketches, second: the tail
+ *        group); the rest is scratch.
+ * Precision: each row block is sketched first in 32-bit fixed point at a
+ * scale from its sampled leading rows, and that pass is kept only when no
+ * entry left the fixed-point range and the modelled rounding error of every
+ * sketch window is at most 3e-6 of the window's norm (at most 5.2e-6 in
+ * the worst case over the rounding, in expectation over the hash signs).
+ * Otherwise the block is redone at a scale from its own root mean square,
+ * which bounds the expected relative error by 2^-18 (3.8e-6) of the
+ * block's 2-norm for any finite input; entries far above the root mean
+ * square are then added as float atomics, and NaN / Inf propagate.  Float
+ * sums are accumulated in a scheduling-dependent order, so results may
  * differ between runs by rounding; integer-valued inputs whose partial sums
  * stay below 2^24 are exact.  Errors: FCS_EINVAL, FCS_ENOMEM, FCS_EDEVICE. */
 FCS_API fcs_status fcs_sketch_dense(fcs_plan_t plan, const float *T, float *out,
@@ -187,6 +200,10 @@ FCS_API fcs_status fcs_sketch_dense(fcs_plan_t plan, const float *T, float *out,
  *   out  device, float, D x J~; overwritten
  * nnz = 0 gives a zero sketch.  Indices are trusted: out-of-range indices
  * are undefined behaviour (validate on the host if they are untrusted).
+ * Precision: an entry is summed in 32-bit fixed point (with every wrap of a
+ * bin carried exactly) only when rounding moves it by at most 2^-17 of its
+ * own magnitude; other entries are added as float atomics, so the expected
+ * relative error from rounding is at most 2^-17 (7.6e-6) for any input.
  * Errors: FCS_EINVAL, FCS_ENOMEM, FCS_EDEVICE. */
 FCS_API fcs_status fcs_sketch_coo(fcs_plan_t plan, int64_t nnz, const int32_t *idx,
                           const float *val, float *out, void *ws,
@@ -212,7 +229,9 @@ FCS_API fcs_status fcs_sketch_cp(fcs_plan_t plan, int64_t R, const float *const 
  * plan: 0, 1 index A, 2, 3 index B).  Computed as the linear convolution of
  * the order-2 sketches of A and B (FCS is a convolution of mode sketches),
  * each summed exactly in 64-bit fixed point from the float entries (the
- * largest magnitude of a matrix maps into [2^27, 2^28)), then transformed,
+ * largest magnitude of a matrix maps into [2^(B-1), 2^B) with
+ * B = min(40, 62 - ceil(log2 of its entry count)), so rounding moves the
+ * sketch by at most sqrt(entries) 2^-B of its norm), then transformed,
  * multiplied and inverted in float.
  *   plan  order-4 plan; (J_0 + J_1 - 1) and (J_2 + J_3 - 1) 64-bit bins must
  *         fit in LDS (about 20000 bins)

@@ -418,9 +418,13 @@ __device__ __forceinline__ void sum_slices(const CpDesc &c, int d) {
 // Order-2 FCS of the I_a x I_b column-major matrix M under the hash words
 // ta (mode a) and tb (mode b) of one sketch: y[h_a(i) + h_b(j)] +=
 // s_a(i) s_b(j) M[i, j] for nb = J_a + J_b - 1 bins, written to y (global).
-// Entries are quantised to integers (the largest magnitude maps into
-// [2^27, 2^28)) and summed exactly in 64-bit LDS bins; lds must hold nb
-// 64-bit words.  A matrix with a non-finite entry gives NaN bins.
+// Entries are quantised to 64-bit integers and summed exactly in 64-bit LDS
+// bins: the largest magnitude maps into [2^(B-1), 2^B) with
+// B = min(40, 62 - ceil(log2(I_a I_b))), so no bin can overflow and rounding
+// moves each entry by at most 2^-B of that largest magnitude (relative error
+// of the sketch at most sqrt(I_a I_b) 2^-B, below 1e-7 up to 2^20 entries).
+// lds must hold nb 64-bit words.  A matrix with a non-finite entry gives NaN
+// bins.
 // With STRIDED, entry k of the matrix is M[k * stride] (a slice of a
 // larger tensor whose other index varies fastest).
 template <int T, bool STRIDED = false>
@@ -461,9 +465,11 @@ __device__ __forceinline__ void kron_factor_sketch(const float *__restrict__ M, 
         for (int j = t; j < nb; j += T) y[j] = __builtin_nanf("");
         return;
     }
-    int F = 27;
-    if (M0 > 0.f) F = 28 - __builtin_amdgcn_frexp_expf(M0);
-    F = max(-120, min(120, F));
+    const int lgn = n > 1 ? 64 - __clzll((unsigned long long)(n - 1)) : 0;
+    const int B = min(40, 62 - lgn);
+    int F = B - 1;
+    if (M0 > 0.f) F = B - __builtin_amdgcn_frexp_expf(M0);
+    F = max(-120, min(127, F));
     const float scale = ldexpf(1.0f, F);
     for (int j = t; j < nb; j += T) bins[j] = 0ull;
     __syncthreads();
@@ -472,7 +478,7 @@ __device__ __forceinline__ void kron_factor_sketch(const float *__restrict__ M, 
     for (int64_t k = t; k < n; k += T) {
         const uint32_t wa = ta[i], wb = tb[j];
         const int bin = (int)(wa & FCS_H_MASK) + (int)(wb & FCS_H_MASK);
-        long long qv = (long long)__float2int_rn(M[STRIDED ? k * stride : k] * scale);
+        long long qv = __float2ll_rn(M[STRIDED ? k * stride : k] * scale);
         if ((wa ^ wb) & FCS_S_BIT) qv = -qv;
         atomicAdd(&bins[bin], (unsigned long long)qv);
         i += st_i;
@@ -483,8 +489,9 @@ __device__ __forceinline__ void kron_factor_sketch(const float *__restrict__ M, 
         }
     }
     __syncthreads();
-    const float inv = ldexpf(1.0f, -F);
-    for (int b = t; b < nb; b += T) y[b] = (float)(long long)bins[b] * inv;
+    // 2^-F in two normal factors (F may reach 127)
+    const float inv1 = ldexpf(1.0f, -(F / 2)), inv2 = ldexpf(1.0f, -(F - F / 2));
+    for (int b = t; b < nb; b += T) y[b] = (float)(long long)bins[b] * inv1 * inv2;
     __syncthreads();
 }
 

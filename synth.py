@@ -303,3 +303,70 @@ def coo_nnz_sizes(seed: int, count: int, lo: float = 1e4, hi: float = 1e8) -> li
     """nnz of the pre-staged COO tensors: log-uniform in [lo, hi]."""
     g = rng(seed, 13)
     return [int(np.exp(g.uniform(np.log(lo), np.log(hi)))) for _ in range(count)]
+
+
+# ----------------------------------------------------------------------------
+# inputs with a wide dynamic range (scales vary across rows and entries)
+# ----------------------------------------------------------------------------
+WIDE_KINDS = ("spike", "spike_each_slab", "leading_rows_large", "rows_after_16_small",
+              "log_uniform_rows", "decaying_rows", "zero_head_tiny")
+
+
+def wide_range_tensor(seed: int, I, kind: str, stream: int = 0) -> np.ndarray:
+    """vec(T) (mode 0 fastest) of a float32 tensor whose magnitudes vary
+    widely across its rows (mode-0 fibres).  A slab is the set of rows that
+    share the last-mode index; ``r`` below is a row's position in its slab.
+
+    * ``spike``: N(0, 1e-6) variance entries (sd 1e-3) and a single entry
+      1e3 in row 3 of the first slab;
+    * ``spike_each_slab``: the same with one 1e3 entry in row 3 of every slab;
+    * ``leading_rows_large``: N(0,1), rows r < 16 of every slab times 100;
+    * ``rows_after_16_small``: N(0,1), rows r >= 16 times 1e-2;
+    * ``log_uniform_rows``: N(0,1), each row times 10^U(-3, 3);
+    * ``decaying_rows``: N(0,1), row r times 2^(-r/8);
+    * ``zero_head_tiny``: rows r < 16 zero, the others N(0, 1e-12) (sd 1e-6).
+    """
+    I = [int(i) for i in I]
+    I0 = I[0]
+    rows = int(np.prod(I[1:]))
+    slab = int(np.prod(I[1:-1]))
+    T = dense_tensor(seed, I, stream).reshape(rows, I0)
+    r = (np.arange(rows) % slab)
+    g = rng(seed, stream, 99)
+    if kind in ("spike", "spike_each_slab"):
+        T *= np.float32(1e-3)
+        hot = [3 % slab] if kind == "spike" else list(range(3 % slab, rows, slab))
+        for row in hot:
+            T[row, 17 % I0] = np.float32(1e3)
+    elif kind == "leading_rows_large":
+        T[r < 16] *= np.float32(100.0)
+    elif kind == "rows_after_16_small":
+        T[r >= 16] *= np.float32(1e-2)
+    elif kind == "log_uniform_rows":
+        T *= (10.0 ** g.uniform(-3.0, 3.0, rows)).astype(np.float32)[:, None]
+    elif kind == "decaying_rows":
+        T *= (2.0 ** (-r / 8.0)).astype(np.float32)[:, None]
+    elif kind == "zero_head_tiny":
+        T *= np.float32(1e-6)
+        T[r < 16] = 0.0
+    else:
+        raise ValueError(f"unknown kind {kind!r}")
+    return np.ascontiguousarray(T.reshape(-1))
+
+
+def wide_range_values(seed: int, nnz: int, kind: str, head: int = 16384) -> np.ndarray:
+    """COO values with a wide dynamic range: ``large_head`` (N(0,1) with the
+    first ``head`` values times 1e3), ``zero_head_tiny`` (first ``head`` zero,
+    the rest N(0,1) times 1e-6), ``log_uniform`` (N(0,1) times 10^U(-6, 6))."""
+    g = rng(seed, 5)
+    v = g.standard_normal(nnz)
+    if kind == "large_head":
+        v[:head] *= 1e3
+    elif kind == "zero_head_tiny":
+        v *= 1e-6
+        v[:head] = 0.0
+    elif kind == "log_uniform":
+        v *= 10.0 ** g.uniform(-6.0, 6.0, nnz)
+    else:
+        raise ValueError(f"unknown kind {kind!r}")
+    return v.astype(np.float32)
