@@ -224,6 +224,23 @@ FCS_API fcs_status fcs_sketch_cp(fcs_plan_t plan, int64_t R, const float *const 
                          const float *lambda, float *out, float *spec,
                          void *ws, size_t ws_bytes, void *stream);
 
+/* Allocation-free variant of fcs_sketch_cp, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same arguments, results and
+ * errors as fcs_sketch_cp except the workspace: the chunk partial spectra
+ * and slice terms live in a device array of FCS_NOALLOC_SCRATCH_BYTES
+ * inside the library (one per device, held until the process ends).  When
+ * the partials of fcs_sketch_cp's rank chunks would not fit, fewer chunks
+ * are used (the rank sums then group differently, a rounding-level
+ * difference); a plan whose slice terms alone exceed the array fails with
+ * FCS_ENOMEM before anything is enqueued.  The call makes no allocation.
+ * All calls on one device share its array: calls that overlap on a device
+ * (concurrent streams or threads) race and must be serialised by the
+ * caller. */
+#define FCS_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+FCS_API fcs_status fcs_sketch_cp_noalloc(fcs_plan_t plan, int64_t R, const float *const *U,
+                                 const float *lambda, float *out, float *spec, void *stream);
+
 /* Kronecker product compression, Section 4.3: the FCS of A (x) B viewed as
  * the order-4 tensor T[i0, i1, i2, i3] = A[i0, i1] B[i2, i3] (modes of the
  * plan: 0, 1 index A, 2, 3 index B).  Computed as the linear convolution of

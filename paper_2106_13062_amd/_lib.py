@@ -54,6 +54,7 @@ SIGNATURES = {
     "fcs_sketch_dense": (I32, [P, P, P, P, SZ, P]),
     "fcs_sketch_coo": (I32, [P, I64, P, P, P, P, SZ, P]),
     "fcs_sketch_cp": (I32, [P, I64, ctypes.POINTER(P), P, P, P, P, SZ, P]),
+    "fcs_sketch_cp_noalloc": (I32, [P, I64, ctypes.POINTER(P), P, P, P, P]),
     "fcs_sketch_spectrum": (I32, [P, P, P, P, SZ, P]),
     "fcs_sketch_kron": (I32, [P, P, P, P, P, P, SZ, P]),
     "fcs_sketch_contraction": (I32, [P, I64, P, P, P, P, P, SZ, P]),

@@ -20,6 +20,7 @@
 #include "fcs_internal.h"
 
 #include <algorithm>
+#include <mutex>
 
 #include "cp_tile.h"
 #include "fft.h"
@@ -459,9 +460,10 @@ size_t fcs_ws_free_mode(const fcs_plan *p, int64_t Pn) {
     return align256((size_t)p->D * Pn * Jmax * 4) + align256((size_t)Pn * Imax * p->D * 4);
 }
 
-extern "C" fcs_status fcs_sketch_cp(fcs_plan_t p, int64_t R, const float *const *U, const float *lambda,
-                                    float *out, float *spec, void *ws, size_t ws_bytes, void *stream) {
-    fcs_clear_error();
+// Argument checks shared by fcs_sketch_cp and fcs_sketch_cp_noalloc
+// (nothing is enqueued before they pass).
+static fcs_status cp_check_args(const fcs_plan *p, int64_t R, const float *const *U, const float *out,
+                                const float *spec) {
     if (!p || !p->bound) FCS_FAIL(FCS_EINVAL, "plan is null or not bound");
     if (p->P == 0) FCS_FAIL(FCS_EUNSUPPORTED, "no transform length fits this plan");
     if (R < 0) FCS_FAIL(FCS_EINVAL, "R < 0");
@@ -472,7 +474,13 @@ extern "C" fcs_status fcs_sketch_cp(fcs_plan_t p, int64_t R, const float *const 
         if (p->I[n] >= FCS_MAX_GATHER_INDEX) FCS_FAIL(FCS_EUNSUPPORTED, "CP sketches need I_n < 2^30");
     for (int n = 0; R > 0 && n < p->N; ++n)
         if (!U[n]) FCS_FAIL(FCS_EINVAL, "null factor %d", n);
-    hipStream_t s = (hipStream_t)stream;
+    return FCS_OK;
+}
+
+// The CP sketch with `nchunks` rank chunks; buf holds the chunk partial
+// spectra and the slice terms (cp_partial_bytes + cp_ytmp_bytes).
+static fcs_status cp_run(const fcs_plan *p, int64_t R, const float *const *U, const float *lambda, float *out,
+                         float *spec, void *buf, int nchunks, hipStream_t s) {
     if (R == 0) {
         if (out) {
             fcs_status st = fcs_zero_fill(out, (int64_t)p->D * p->Jt, s);
@@ -481,24 +489,89 @@ extern "C" fcs_status fcs_sketch_cp(fcs_plan_t p, int64_t R, const float *const 
         if (spec) return fcs_zero_fill(spec, (int64_t)p->D * p->Qh * p->P * 2, s);
         return FCS_OK;
     }
-    const size_t need = fcs_ws_cp(p, R);
-    if (!ws || ws_bytes < need) FCS_FAIL(FCS_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, need);
-    if (!fcs_aligned(ws, 16)) FCS_FAIL(FCS_EINVAL, "workspace not 16-byte aligned");
     CpDesc c{};
     desc_from_plan(c, p);
     c.kind = FCS_DESC_CP;
     for (int n = 0; n < p->N; ++n) c.U[n] = U[n];
     c.lambda = lambda;
     c.R = (int)R;
-    c.nchunks = cp_chunks(p, R);
+    c.nchunks = nchunks;
     c.rchunk = (int)fcs_ceil_div(R, c.nchunks);
-    c.partial = (float2 *)ws;
-    c.ytmp = (float *)((char *)ws + cp_partial_bytes(p, c.nchunks));
+    c.partial = (float2 *)buf;
+    c.ytmp = (float *)((char *)buf + cp_partial_bytes(p, c.nchunks));
     c.out = out;
     c.spec = (float2 *)spec;
     FCS_DISPATCH_FFT(p->P, (launch_cp<PP>(c, s)));
     FCS_LAUNCH_CHECK();
     return FCS_OK;
+}
+
+extern "C" fcs_status fcs_sketch_cp(fcs_plan_t p, int64_t R, const float *const *U, const float *lambda,
+                                    float *out, float *spec, void *ws, size_t ws_bytes, void *stream) {
+    fcs_clear_error();
+    fcs_status st = cp_check_args(p, R, U, out, spec);
+    if (st != FCS_OK) return st;
+    if (R > 0) {
+        const size_t need = fcs_ws_cp(p, R);
+        if (!ws || ws_bytes < need) FCS_FAIL(FCS_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, need);
+        if (!fcs_aligned(ws, 16)) FCS_FAIL(FCS_EINVAL, "workspace not 16-byte aligned");
+    }
+    return cp_run(p, R, U, lambda, out, spec, ws, R > 0 ? cp_chunks(p, R) : 1, (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free CP sketch.  Its chunk partials and slice terms live in a
+// file-scope device array of FCS_NOALLOC_SCRATCH_BYTES (each device the
+// library runs on holds its own copy until the process ends).  Host code
+// never passes the array's name to a kernel: its device address is looked
+// up once per device with hipGetSymbolAddress on the first call made with
+// that device current, and kept.  Every call on a device shares that
+// device's array, so calls that overlap on one device race.  Nothing needs
+// to start at zero: the kernels overwrite every word they later read.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[FCS_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+fcs_status noalloc_scratch(void **out) {
+    int dev = 0;
+    FCS_HIP_CHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) FCS_FAIL(FCS_EUNSUPPORTED, "device %d beyond %d", dev, NOALLOC_MAX_DEVICES);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        FCS_HIP_CHECK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) FCS_FAIL(FCS_EDEVICE, "no device address for the scratch array");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return FCS_OK;
+}
+}  // namespace
+
+extern "C" fcs_status fcs_sketch_cp_noalloc(fcs_plan_t p, int64_t R, const float *const *U, const float *lambda,
+                                            float *out, float *spec, void *stream) {
+    fcs_clear_error();
+    fcs_status st = cp_check_args(p, R, U, out, spec);
+    if (st != FCS_OK) return st;
+    // the rank chunks of fcs_sketch_cp, fewer when their partials would not
+    // fit the array (the sums then group the ranks differently)
+    int nch = R > 0 ? cp_chunks(p, R) : 1;
+    while (nch > 1 && cp_partial_bytes(p, nch) + cp_ytmp_bytes(p) > FCS_NOALLOC_SCRATCH_BYTES) --nch;
+    const size_t need = cp_partial_bytes(p, nch) + cp_ytmp_bytes(p);
+    if (R > 0 && need > FCS_NOALLOC_SCRATCH_BYTES)
+        FCS_FAIL(FCS_ENOMEM, "slice terms need %zu bytes, more than the %zu-byte scratch array of "
+                             "fcs_sketch_cp_noalloc (use fcs_sketch_cp with a workspace)",
+                 need, (size_t)FCS_NOALLOC_SCRATCH_BYTES);
+    void *buf = nullptr;
+    if (R > 0) {
+        st = noalloc_scratch(&buf);
+        if (st != FCS_OK) return st;
+    }
+    return cp_run(p, R, U, lambda, out, spec, buf, nch, (hipStream_t)stream);
 }
 
 extern "C" fcs_status fcs_sketch_kron(fcs_plan_t p, const float *A, const float *B, float *out, float *spec,

@@ -146,6 +146,28 @@ class Plan:
                                        _stream(stream)))
         return out, spec
 
+    def sketch_cp_noalloc(self, U, lam=None, out=None, spec=None, want_out=True, want_spec=False, stream=None):
+        """fcs_sketch_cp_noalloc: the CP sketch with the library's own
+        device scratch array instead of a workspace (the library allocates
+        nothing; outputs not given are allocated here)."""
+        if len(U) != self.N:
+            raise ValueError("need N factors")
+        R = int(U[0].shape[0])
+        for n, u in enumerate(U):
+            _need(u, torch.float32, f"U[{n}]")
+            if tuple(u.shape) != (R, self.I[n]):
+                raise ValueError(f"U[{n}] must be R x I_n = {(R, self.I[n])}")
+        if lam is not None:
+            _need(lam, torch.float32, "lambda")
+        if want_out and out is None:
+            out = torch.empty((self.D, self.Jt), dtype=torch.float32, device=self.device)
+        if want_spec and spec is None:
+            spec = torch.empty((self.D, self.spec_len, 2), dtype=torch.float32, device=self.device)
+        ptrs = (ctypes.c_void_p * self.N)(*[u.data_ptr() for u in U])
+        C.check(self.lib.fcs_sketch_cp_noalloc(self._h, R, ptrs, _ptr(lam), _ptr(out), _ptr(spec),
+                                               _stream(stream)))
+        return out, spec
+
     def sketch_kron(self, A: torch.Tensor, B: torch.Tensor, out=None, spec=None, want_out=True,
                     want_spec=False, ws=None, stream=None):
         """Kronecker product A (x) B of an order-4 plan: A is I_0 x I_1 and B
