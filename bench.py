@@ -109,8 +109,9 @@ def dense_cpu_baseline(cfg, T, Jt, sample_rows):
                       f"all {cfg.D} sketches, {dt:.2f} s, scaled to the full tensor"}
 
 
-def cp_workload(args, torch, dev, cfg, pairs=0):
-    """CP sketch (and optionally T(I, u, v) for `pairs` vector pairs)."""
+def cp_workload(args, torch, dev, cfg, pairs=0, inner=False):
+    """CP sketch (and optionally T(I, u, v) for `pairs` vector pairs, and the
+    inner product with a second CP tensor's sketch)."""
     import synth
     from paper_2106_13062_amd import Plan
     U = cfg.factors()
@@ -136,6 +137,46 @@ def cp_workload(args, torch, dev, cfg, pairs=0):
            "P": plan.P, "Q": plan.Q, "ms": ms, "sketches_per_s": cfg.D / (ms * 1e-3),
            "fft_gflop": fft_flop / 1e9, "fft_tflops": fft_flop / (ms * 1e-3) / 1e12,
            "frac_fp32_peak": fft_flop / (ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS}
+    if inner:
+        # the order-3 I_n = 100 outputs: the sketch of a second random rank-R
+        # CP tensor, the median over D of the sketch inner products
+        # (Proposition 1), and the general-formula sketch of the
+        # materialised tensor
+        V = cfg.factors(stream=1)
+        Vd = [torch.from_numpy(np.ascontiguousarray(v.T)).to(dev) for v in V]
+        outb = torch.empty_like(out)
+        wsi = plan.workspace(3)
+
+        def inner_step():
+            plan.sketch_cp(Ud, out=out, ws=ws, stream=stream)
+            plan.sketch_cp(Vd, out=outb, ws=ws, stream=stream)
+            return plan.contract_inner(out, outb, ws=wsi, stream=stream)
+
+        med, per_d = inner_step()
+        ims, _ = event_timer(torch, stream, inner_step, max(3, args.steps // 2))
+        U64 = [u.astype(np.float64) for u in U]
+        V64 = [v.astype(np.float64) for v in V]
+        G = np.ones((R, R))
+        for u, v in zip(U64, V64):
+            G *= u.T @ v
+        exact = float(G.sum())                 # <M, N> of the two CP tensors
+        GM = np.ones((R, R))
+        GN = np.ones((R, R))
+        for u, v in zip(U64, V64):
+            GM *= u.T @ u
+            GN *= v.T @ v
+        # the size of one sketch's estimation error, ||M|| ||N|| / sqrt(J~)
+        noise = float(np.sqrt(GM.sum() * GN.sum() / plan.Jt))
+        est = float(med.cpu()[0])
+        Tm = np.einsum("ir,jr,kr->kji", *U64).reshape(-1).astype(np.float32)   # vec order, mode 0 fastest
+        plan.sketch_cp(Ud, out=out, ws=ws, stream=stream)
+        yd = plan.sketch_dense(torch.from_numpy(Tm).to(dev)).cpu().numpy().astype(np.float64)
+        yc = out.cpu().numpy().astype(np.float64)
+        res.update({"inner_ms": ims, "inner_estimate": est, "inner_exact": exact,
+                    "inner_rel_error_vs_exact": abs(est - exact) / max(abs(exact), 1e-300),
+                    "inner_noise_scale": noise,
+                    "inner_per_sketch": [float(x) for x in per_d.cpu().numpy()],
+                    "bruteforce_rel_l2": float(np.linalg.norm(yc - yd) / np.linalg.norm(yd))})
     if pairs:
         uv = synth.unit_vectors(cfg.data_seed, 2 * pairs, cfg.I[1], stream=5)
         u = torch.from_numpy(uv[:pairs]).to(dev)
@@ -400,7 +441,7 @@ def serve_requests(srv, args, rate, count, seed):
 
 
 def rtpm_workload(args, torch, dev):
-    """Sketched robust tensor power method (Section 5, RTPM) in the setting of
+    """Sketched robust tensor power method (Section 4.1.1, RTPM) in the setting of
     the paper's synthetic experiment: a symmetric 100^3 tensor of CP rank 10
     (orthonormal basis, unit weights) plus Gaussian noise at level 0.01 (read
     as ||N|| = 0.01 ||T||), D = 2 sketches, 15 starts, 20 power iterations,
@@ -446,7 +487,7 @@ def rtpm_workload(args, torch, dev):
 
 
 def rtpm_asym_workload(args, torch, dev):
-    """RTPM by alternating rank-1 updates (the asymmetric form of Section 5)
+    """RTPM by alternating rank-1 updates (the asymmetric form of Section 4.1.1)
     on an asymmetric 100^3 tensor of CP rank 10 (three independent
     orthonormal factors, unit weights) plus Gaussian noise at level 0.01
     (relative), D = 10 (the paper's asymmetric experiments use 10 and 15),
@@ -526,7 +567,7 @@ def rtpm50_workload(args, torch, dev):
 
 
 def als_workload(args, torch, dev):
-    """Sketched alternating least squares (Section 5, ALS) in the setting of
+    """Sketched alternating least squares (Section 4.1.2, ALS) in the setting of
     the paper's synthetic experiment: an asymmetric 400^3 tensor of CP rank
     10 (three independent orthonormal factors, unit weights) plus Gaussian
     noise at level 0.01 (read as ||N|| = 0.01 ||T||), D = 10 sketches,
@@ -759,7 +800,7 @@ def main():
         return
     if args.mode == "cp":
         import synth
-        print(json.dumps({"cp100": cp_workload(args, torch, dev, synth.CP100),
+        print(json.dumps({"cp100": cp_workload(args, torch, dev, synth.CP100, inner=True),
                           "cp10k": cp_workload(args, torch, dev, synth.CP10K, pairs=synth.CP10K.pairs)}),
               flush=True)
         return
@@ -768,7 +809,7 @@ def main():
     if args.mode == "full":
         import synth
         log("secondary: cp100")
-        secondary["cp100"] = cp_workload(args, torch, dev, synth.CP100)
+        secondary["cp100"] = cp_workload(args, torch, dev, synth.CP100, inner=True)
         log("secondary: cp10k + T(I,u,v)")
         secondary["cp10k"] = cp_workload(args, torch, dev, synth.CP10K, pairs=synth.CP10K.pairs)
         log("secondary: coo")

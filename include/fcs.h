@@ -66,7 +66,9 @@ typedef enum {
     FCS_OK = 0,
     FCS_EINVAL = 1,          /* bad argument (shape, pointer, size, mode)   */
     FCS_ENOMEM = 2,          /* caller buffer smaller than required         */
-    FCS_EADMIT = 3,          /* batch rejected by the admission bound       */
+    FCS_EADMIT = 3,          /* request over the serving admission cap (the
+                                serving layer reports it; no call here
+                                returns it)                                 */
     FCS_EDEVICE = 4,         /* a HIP call or kernel launch failed          */
     FCS_EUNSUPPORTED = 5     /* valid request outside this build's limits   */
 } fcs_status;

@@ -380,7 +380,7 @@ def contraction_fcs(A, B, h, s, J) -> np.ndarray:
 def decompress_median(Y, hs, ss, I) -> np.ndarray:
     """The tensor recovered from D sketches Y (D x J~): per sketch, entry i
     is S(i) FCS[H(i)] (the decompression rule of Section 4.3, for any
-    order), and the D estimates are reduced by the median (Section 5: the
+    order), and the D estimates are reduced by the median (Section 4: the
     median over independent sketches)."""
     est = np.stack([kron_decompress(Y[d], hs[d], ss[d], I) for d in range(len(Y))])
     return median(est, axis=0)
@@ -410,7 +410,7 @@ def kron_decompress(y, h, s, I) -> np.ndarray:
 
 
 # ---------------------------------------------------------------------------
-# Robust tensor power method on sketches (Section 5: RTPM for a symmetric
+# Robust tensor power method on sketches (Section 4.1.1: RTPM for a symmetric
 # order-3 tensor, with T(I,u,u) and T(u,u,u) estimated from D sketches as in
 # Section 4.1).  For each component: power iterations u <- T(I,u,u) /
 # ||T(I,u,u)|| from several starting vectors, the eigenvalue T(u,u,u) of
@@ -452,7 +452,7 @@ def rtpm(Y, hs, ss, J, rank: int, inits, iters: int):
 
 
 def rtpm_asym(Y, hs, ss, J, rank: int, inits, iters: int):
-    """RTPM for an asymmetric order-3 tensor (Section 5: the power iteration
+    """RTPM for an asymmetric order-3 tensor (Section 4.1.1: the power iteration
     becomes an alternating rank-1 update).  Y: D x J~ sketches; inits:
     rank x L x 3 x I_max starting vectors (mode n uses the first I_n
     entries of slot n).  Per component and start: u <- T(I,v,w), then
@@ -487,7 +487,7 @@ def rtpm_asym(Y, hs, ss, J, rank: int, inits, iters: int):
 
 
 # ---------------------------------------------------------------------------
-# Alternating least squares on sketches (Section 5, ALS for an order-3
+# Alternating least squares on sketches (Section 4.1.2, ALS for an order-3
 # tensor).  Mode n is updated from the product of the mode-n unfolding with
 # the Khatri-Rao product of the other factors; column r of that product is
 # the contraction of T with the r-th columns of the other factors at their

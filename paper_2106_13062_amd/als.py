@@ -1,4 +1,4 @@
-"""Alternating least squares on fast count sketches (Section 5 of the paper:
+"""Alternating least squares on fast count sketches (Section 4.1.2 of the paper:
 ALS for an order-3 tensor, with the contractions of Section 4.1 estimated
 from D sketches).
 

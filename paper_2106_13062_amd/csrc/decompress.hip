@@ -3,7 +3,7 @@
 // order: per sketch d, entry i of the recovered tensor is S_d(i) y_d[H_d(i)]
 // with H_d = sum_n h_n(i_n) and S_d = prod_n s_n(i_n).  The D estimates are
 // reduced by their median, since the method keeps D independent sketches and
-// returns the median (Section 5).
+// returns the median (Section 4).
 //
 // The output is written in a caller-chosen mode order, fastest first.  Its
 // dimensions split into inner ones [0, ks) and outer ones [ks, N).  The outer

@@ -1,4 +1,4 @@
-"""Robust tensor power method on fast count sketches (Section 5 of the
+"""Robust tensor power method on fast count sketches (Section 4.1.1 of the
 paper: RTPM for a symmetric order-3 tensor, with the contractions of
 Section 4.1 estimated from D sketches).
 

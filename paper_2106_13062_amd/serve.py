@@ -13,7 +13,8 @@ and forms launch groups: waiting ``contract`` requests against the same
 resident sketch are merged into one multi-pair launch (continuous batching:
 whatever arrived while the device was busy goes out together), builds go out
 one per launch.  The ``Server`` owns the device side: a cache of bound plans
-per (seed, shape, hash lengths, D, L) so hash tables stay resident, the
+per (seed, shape, hash lengths, D, L) so hash tables stay resident (bounded,
+least recently used unpinned plans go first), the
 resident sketch spectra, several streams of default priority on which
 launch groups overlap, and completion events from which latency is taken
 (arrival on the host clock to the first host poll that sees the group's
@@ -46,6 +47,14 @@ class Request:
     result: Any = None           # (tensor, row) or tensor
 
 
+class AdmissionError(C.FcsError):
+    """A request whose footprint alone exceeds the admission cap (status
+    FCS_EADMIT)."""
+
+    def __init__(self, message: str):
+        super().__init__(C.FCS_EADMIT, message)
+
+
 class Scheduler:
     """Admission by device-memory footprint and launch grouping (no device
     calls, so it is testable on the host)."""
@@ -61,7 +70,7 @@ class Scheduler:
 
     def submit(self, req: Request):
         if req.footprint + self.resident_bytes > self.cap:
-            raise ValueError(f"request {req.rid} needs {req.footprint} bytes, more than the cap allows")
+            raise AdmissionError(f"request {req.rid} needs {req.footprint} bytes, more than the cap allows")
         self.waiting.append(req)
 
     def fits(self, nbytes: int) -> bool:
@@ -106,15 +115,73 @@ class Scheduler:
         self.inflight_groups -= 1
 
 
+class PlanCache:
+    """Bound plans by key (seed, mode sizes, hash lengths, D, L), so that
+    hash tables stay resident between requests.  A plan that a resident
+    sketch or a staged input uses is pinned; when the cached table bytes
+    exceed `limit_bytes`, unpinned plans go out least recently used first,
+    and their bytes leave the scheduler's resident total.  `make(key)` builds
+    a plan; `nbytes(plan)` gives its device bytes; `close(plan)` releases it
+    (no device calls here, so the policy is testable on the host)."""
+
+    def __init__(self, sched: Scheduler, limit_bytes: float, make, nbytes, close=lambda p: None):
+        self.sched = sched
+        self.limit = float(limit_bytes)
+        self.make, self.nbytes, self.close = make, nbytes, close
+        self.plans: collections.OrderedDict = collections.OrderedDict()
+        self.pins: collections.Counter = collections.Counter()
+        self.bytes = 0
+
+    def get(self, key):
+        p = self.plans.get(key)
+        if p is not None:
+            self.plans.move_to_end(key)
+            return p
+        p = self.make(key)
+        nb = int(self.nbytes(p))
+        self.plans[key] = p
+        self.bytes += nb
+        self.sched.resident_bytes += nb
+        self._evict(keep=key)
+        return p
+
+    def pin(self, key):
+        self.pins[key] += 1
+
+    def unpin(self, key):
+        self.pins[key] -= 1
+        if self.pins[key] <= 0:
+            del self.pins[key]
+        self._evict(keep=None)
+
+    def _evict(self, keep):
+        for k in list(self.plans):
+            if self.bytes <= self.limit:
+                break
+            if k == keep or self.pins.get(k, 0) > 0:
+                continue
+            p = self.plans.pop(k)
+            nb = int(self.nbytes(p))
+            self.bytes -= nb
+            self.sched.resident_bytes -= nb
+            self.close(p)
+
+
+def _plan_key(I, J, D, seed, L=0):
+    return (int(seed) & ((1 << 64) - 1), tuple(int(i) for i in I), tuple(int(j) for j in J), int(D), int(L))
+
+
 class Server:
     """Device side of the serving loop."""
 
     def __init__(self, device=None, streams: int = 4, cap_bytes: float = 200e9, max_group: int = 256,
-                 max_inflight: int = 8):
+                 max_inflight: int = 8, plan_cache_bytes: float = 16e9):
         self.device = torch.device("cuda") if device is None else torch.device(device)
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(streams)]
         self.sched = Scheduler(cap_bytes, max_group, max_inflight)
-        self.plans: dict = {}
+        self.plans = PlanCache(self.sched, plan_cache_bytes,
+                               make=lambda k: Plan(k[1], k[2], k[3], k[0], L=k[4], device=self.device),
+                               nbytes=lambda p: p.tables.numel(), close=lambda p: p.close())
         self.resident: dict = {}       # name -> (plan, spec, bank_u, bank_v)
         self.inputs: dict = {}         # name -> ("cp", plan, U) or ("coo", plan, idx, val)
         self.inflight: list = []       # (event, members, nbytes)
@@ -122,27 +189,45 @@ class Server:
 
     # ------------------------------------------------------------ resources
     def plan(self, I, J, D, seed, L=0) -> Plan:
-        key = (int(seed), tuple(int(i) for i in I), tuple(int(j) for j in J), int(D), int(L))
+        key = _plan_key(I, J, D, seed, L)
         p = self.plans.get(key)
-        if p is None:
-            p = Plan(I, J, D, seed, L=L, device=self.device)
-            self.plans[key] = p
-            self.sched.resident_bytes += p.tables.numel()
+        p.cache_key = key
         return p
+
+    @staticmethod
+    def _bytes(tensors):
+        flat = [x for t in tensors for x in (t if isinstance(t, (list, tuple)) else [t])]
+        return sum(t.numel() * t.element_size() for t in flat)
 
     def add_resident_sketch(self, name, plan: Plan, spec: torch.Tensor, bank_u: torch.Tensor,
                             bank_v: torch.Tensor):
         """A sketch spectrum kept on the device with a bank of (u, v) pairs
-        that contraction requests refer to by index."""
+        that contraction requests refer to by index (pins its plan)."""
         self.resident[name] = (plan, spec, bank_u, bank_v)
-        self.sched.resident_bytes += sum(t.numel() * t.element_size() for t in (spec, bank_u, bank_v))
+        self.sched.resident_bytes += self._bytes((spec, bank_u, bank_v))
+        if getattr(plan, "cache_key", None) is not None:
+            self.plans.pin(plan.cache_key)
+
+    def remove_resident_sketch(self, name):
+        plan, spec, bank_u, bank_v = self.resident.pop(name)
+        self.sched.resident_bytes -= self._bytes((spec, bank_u, bank_v))
+        if getattr(plan, "cache_key", None) is not None:
+            self.plans.unpin(plan.cache_key)
 
     def add_input(self, name, kind, plan: Plan, *tensors):
         """Pre-staged request input: kind "cp" with one argument, the list
-        of N factor tensors (R x I_n); kind "coo" with (idx, val)."""
+        of N factor tensors (R x I_n); kind "coo" with (idx, val) (pins its
+        plan)."""
         self.inputs[name] = (kind, plan, *tensors)
-        flat = [x for t in tensors for x in (t if isinstance(t, (list, tuple)) else [t])]
-        self.sched.resident_bytes += sum(t.numel() * t.element_size() for t in flat)
+        self.sched.resident_bytes += self._bytes(tensors)
+        if getattr(plan, "cache_key", None) is not None:
+            self.plans.pin(plan.cache_key)
+
+    def remove_input(self, name):
+        kind, plan, *tensors = self.inputs.pop(name)
+        self.sched.resident_bytes -= self._bytes(tensors)
+        if getattr(plan, "cache_key", None) is not None:
+            self.plans.unpin(plan.cache_key)
 
     def footprint(self, req: Request) -> int:
         """Device bytes a request holds while in flight (outputs, gathered

@@ -1,4 +1,4 @@
-"""Sketched alternating least squares on the GPU (Section 5, ALS) against the
+"""Sketched alternating least squares on the GPU (Section 4.1.2, ALS) against the
 FP64 oracle run on the same inputs: same tensor, same hash tables (the
 plan's), same starting factors.  Every weight agrees to 1e-4 relative and
 every factor column to 1 - |cos| <= 1e-4; both recover the planted

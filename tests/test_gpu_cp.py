@@ -76,6 +76,38 @@ def test_cp_matches_dense_of_materialised_tensor():
         assert rel(y[d].cpu().numpy(), yd[d].cpu().numpy()) <= 3 * TOL
 
 
+def test_cp100_inner_product_of_two_cp_tensors():
+    """The order-3 I_n = 100 rank-10 workload (J_n = 64, D = 5): FFT-path
+    sketches of two independent rank-10 CP tensors on the GPU, then the
+    Proposition 1 inner product of each sketch pair and its median over D
+    (fcs_contract_inner), against the oracle's direct-convolution sketches
+    (Section 3.1) and their FP64 inner products.  Scalar bar (Cauchy-Schwarz
+    scale): |x - x_hat| <= 1e-5 ||a_d|| ||b_d|| per sketch and for the
+    median.  The brute-force sketch of the materialised 10^6-entry tensor
+    (general formula, GPU) also matches the FFT path."""
+    cfg = synth.CP100
+    U = cfg.factors()
+    V = cfg.factors(stream=1)
+    plan = Plan(cfg.I, cfg.J, cfg.D, cfg.hash_seed, device=DEV)
+    ya, _ = plan.sketch_cp(dev_factors(U))
+    yb, _ = plan.sketch_cp(dev_factors(V))
+    med, per_d = plan.contract_inner(ya, yb)
+    hs, ss = O.hash_tables(cfg.hash_seed, cfg.D, cfg.I, cfg.J)
+    wa = np.stack([O.fcs_cp_conv(None, U, hs[d], ss[d], cfg.J) for d in range(cfg.D)])
+    wb = np.stack([O.fcs_cp_conv(None, V, hs[d], ss[d], cfg.J) for d in range(cfg.D)])
+    w_med, w_per = O.inner_median(wa, wb)
+    scale = np.linalg.norm(wa, axis=1) * np.linalg.norm(wb, axis=1)
+    got_per = per_d.cpu().numpy()
+    assert np.all(np.abs(got_per - w_per) <= TOL * scale), (got_per, w_per)
+    assert abs(float(med.cpu()[0]) - w_med) <= TOL * float(np.median(scale))
+    # brute force: the general-tensor sketch of the materialised tensor
+    T = O.vec(O.cp_full(None, U)).astype(np.float32)
+    yd = plan.sketch_dense(dev(T)).cpu().numpy()
+    ya = ya.cpu().numpy()
+    for d in range(cfg.D):
+        assert rel(ya[d], yd[d]) <= 3 * TOL, (d, rel(ya[d], yd[d]))
+
+
 def test_cp_rank_zero_and_linearity():
     I, J, D = (20, 30, 40), (16, 16, 16), 3
     plan = Plan(I, J, D, 5, device=DEV)

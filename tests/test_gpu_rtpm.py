@@ -1,4 +1,4 @@
-"""Sketched robust tensor power method on the GPU (Section 5, RTPM) against
+"""Sketched robust tensor power method on the GPU (Section 4.1.1, RTPM) against
 the FP64 oracle run on the same inputs: same tensor, same hash tables (the
 plan's), same starting vectors.  Every eigenvalue agrees to 1e-4 relative
 and every component to 1 - |<u_gpu, u_oracle>| <= 1e-4."""

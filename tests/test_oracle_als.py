@@ -1,4 +1,4 @@
-"""Pin of the oracle's sketched alternating least squares (Section 5, ALS):
+"""Pin of the oracle's sketched alternating least squares (Section 4.1.2, ALS):
 
 * the update of one mode, given the exact unfolding-times-Khatri-Rao product
   of a rank-R tensor and its true other factors, returns exactly the planted

@@ -1,4 +1,4 @@
-"""Pin of the oracle's sketched robust tensor power method (Section 5,
+"""Pin of the oracle's sketched robust tensor power method (Section 4.1.1,
 RTPM): on an orthogonally decomposable symmetric tensor
 sum_r w_r a_r o a_r o a_r (a_r orthonormal, no noise) it must find the planted
 components, in decreasing order of weight, with eigenvalues close to the

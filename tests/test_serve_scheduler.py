@@ -3,7 +3,8 @@ no overtaking, and merging of waiting contraction requests into one launch
 (no device needed)."""
 import pytest
 
-from paper_2106_13062_amd.serve import Request, Scheduler
+from paper_2106_13062_amd import _lib as C
+from paper_2106_13062_amd.serve import AdmissionError, PlanCache, Request, Scheduler
 
 
 def req(rid, kind, key="S", fp=10, t=0.0):
@@ -62,5 +63,50 @@ def test_inflight_limit_and_oversize_request():
     assert len(s.next_groups()) == 0
     s.release(1)
     assert len(s.next_groups()) == 1
-    with pytest.raises(ValueError):
+    with pytest.raises(AdmissionError) as e:
         s.submit(req(9, "cp", fp=2e6))
+    assert e.value.status == C.FCS_EADMIT
+
+
+class _FakePlan:
+    def __init__(self, key, nbytes):
+        self.key, self.nbytes, self.closed = key, nbytes, False
+
+
+def test_plan_cache_evicts_least_recently_used_unpinned_plans():
+    """Hash tables of plans that nothing uses leave the cache (and the
+    admission total) once the cache holds more than its limit; plans of
+    resident sketches or staged inputs stay."""
+    s = Scheduler(cap_bytes=1e9)
+    cache = PlanCache(s, limit_bytes=300, make=lambda k: _FakePlan(k, 100), nbytes=lambda p: p.nbytes,
+                      close=lambda p: setattr(p, "closed", True))
+    a, b, c = cache.get("a"), cache.get("b"), cache.get("c")
+    assert s.resident_bytes == 300 and cache.bytes == 300
+    cache.pin("a")                      # a resident sketch uses plan a
+    cache.get("b")                      # b is now the most recently used
+    d = cache.get("d")                  # over the limit: c goes (a is pinned, b recent)
+    assert c.closed and not a.closed and not b.closed and not d.closed
+    assert set(cache.plans) == {"a", "b", "d"}
+    assert s.resident_bytes == 300
+    e = cache.get("e")                  # b is now the oldest unpinned plan
+    assert b.closed and set(cache.plans) == {"a", "d", "e"}
+    cache.unpin("a")
+    cache.get("f")                      # a is unpinned and oldest
+    assert a.closed and set(cache.plans) == {"d", "e", "f"} and s.resident_bytes == 300
+    assert cache.get("f") is not None and not e.closed
+    # a long stream of distinct keys never grows the resident total past the limit
+    for k in range(100):
+        cache.get(("k", k))
+        assert s.resident_bytes <= 300
+
+
+def test_plan_cache_keeps_pinned_plans_over_the_limit():
+    s = Scheduler(cap_bytes=1e9)
+    cache = PlanCache(s, limit_bytes=150, make=lambda k: _FakePlan(k, 100), nbytes=lambda p: p.nbytes)
+    cache.get("a")
+    cache.pin("a")
+    cache.get("b")
+    cache.pin("b")
+    assert set(cache.plans) == {"a", "b"} and s.resident_bytes == 200
+    cache.unpin("b")                    # b is unpinned: the cache shrinks to its limit
+    assert set(cache.plans) == {"a"} and s.resident_bytes == 100
