@@ -44,6 +44,12 @@ Parity status of each function (what pins it is in ``tests/test_oracle_*.py``):
                           order-4 tensor (Section 4.3).
 * ``contraction_fcs``    pinned against ``fcs_dense`` of the materialised
                           contraction (Section 4.3).
+* ``ts_cp`` / ``hcs_cp`` pinned against ``ts_dense`` / ``hcs_dense`` of the
+                          materialised CP tensor (Definitions 2 and 3; those
+                          two are pinned by explicit loops), ``ts_cp`` also
+                          against the fold of ``fcs_cp_conv``.
+* ``hcs_decompress_median`` pinned by the rule written as explicit loops and
+                          by exact recovery of a lone entry.
 * ``decompress_median``  pinned by the paper's 1-based decompression rule
                           written as explicit loops, by the order-statistic
                           median, by exact recovery of a lone entry and by
@@ -283,6 +289,55 @@ def hcs_dense(T, h, s, J) -> np.ndarray:
         S = S * np.asarray(s[n], dtype=np.float64)[grids[n]]
     np.add.at(out, tuple(idx), S * T)
     return out
+
+
+def ts_cp(lam, U, h, s, J: int) -> np.ndarray:
+    """Tensor sketch of a CP tensor by the FFT form of Definition 2: the sum
+    over r of lambda_r F^-1(prod_n F(CS_n(U_n)(:, r))) with J-point
+    transforms, i.e. the mode-J circular convolution of the modes' count
+    sketches (every mode hashes into the same J bins)."""
+    U = [np.asarray(u, dtype=np.float64) for u in U]
+    R = U[0].shape[1]
+    lam = np.ones(R) if lam is None else np.asarray(lam, dtype=np.float64)
+    P = np.ones((int(J), R), dtype=np.complex128)
+    for n in range(len(U)):
+        P *= np.fft.fft(count_sketch(U[n], h[n], s[n], int(J)), axis=0)
+    return np.fft.ifft(P @ lam).real.copy()
+
+
+def hcs_cp(lam, U, h, s, J) -> np.ndarray:
+    """Higher-order count sketch of a CP tensor (Definition 3, rank-1 form):
+    sum_r lambda_r CS_0(u_r^(0)) o ... o CS_{N-1}(u_r^(N-1)), materialised as
+    a J_0 x ... x J_{N-1} array."""
+    U = [np.asarray(u, dtype=np.float64) for u in U]
+    R = U[0].shape[1]
+    lam = np.ones(R) if lam is None else np.asarray(lam, dtype=np.float64)
+    Y = [count_sketch(U[n], h[n], s[n], int(J[n])) for n in range(len(U))]
+    out = np.zeros(tuple(int(j) for j in J), dtype=np.float64)
+    for r in range(R):
+        t = np.array(lam[r])
+        for n in range(len(U)):
+            t = np.multiply.outer(t, Y[n][:, r])
+        out += t
+    return out
+
+
+def hcs_decompress_median(Y, hs, ss, I) -> np.ndarray:
+    """The tensor recovered from D higher-order count sketches Y[d] (each a
+    J_0 x ... x J_{N-1} array): per sketch, entry i is
+    S(i) HCS[h_0(i_0), ..., h_{N-1}(i_{N-1})], the same decompression rule as
+    for FCS with the bin taken per mode; the D estimates are reduced by the
+    median (Section 4)."""
+    I = tuple(int(i) for i in I)
+    grids = np.meshgrid(*[np.arange(n) for n in I], indexing="ij")
+    est = []
+    for d in range(len(Y)):
+        idx = tuple(np.asarray(hs[d][n])[grids[n]] for n in range(len(I)))
+        S = np.ones(I)
+        for n in range(len(I)):
+            S = S * np.asarray(ss[d][n], dtype=np.float64)[grids[n]]
+        est.append(S * np.asarray(Y[d], dtype=np.float64)[idx])
+    return median(np.stack(est), axis=0)
 
 
 # ---------------------------------------------------------------------------
