@@ -100,6 +100,22 @@ typedef struct {
  * out: host pointer receiving the plan.  Errors: FCS_EINVAL, FCS_EUNSUPPORTED. */
 FCS_API fcs_status fcs_plan_create(const fcs_plan_desc *desc, fcs_plan_t *out);
 
+/* Plan of the higher-order count sketch of Definition 3 (the comparison
+ * sketch of Section 2.2): HCS(T)[j_0, ..., j_{N-1}] sums S T over the
+ * multi-indices with h_n(i_n) = j_n for every n, a J_0 x ... x J_{N-1}
+ * tensor.  Its hash pairs are those of the sketch plan with the same
+ * description (same seed, I_n and J_n), with h_n scaled by the mixed-radix
+ * stride prod_{m<n} J_m: then sum_n h_n(i_n) is the flattened index of
+ * (h_0(i_0), ..., h_{N-1}(i_{N-1})) with mode 0 fastest, and every call that
+ * takes a plan computes the higher-order count sketch instead, flattened to
+ * J~ = prod_n J_n entries: fcs_sketch_dense / _coo for general tensors,
+ * fcs_sketch_cp for CP tensors (the outer products of the rank-1 form are
+ * exactly the linear convolution of the scaled mode sketches),
+ * fcs_decompress (entry = S HCS[h_0, ..., h_{N-1}], median over D),
+ * fcs_contract_inner.  fcs_plan_export returns the scaled hash values.
+ * Errors: as fcs_plan_create; FCS_EUNSUPPORTED when prod_n J_n >= 2^31 - 1. */
+FCS_API fcs_status fcs_plan_create_hcs(const fcs_plan_desc *desc, fcs_plan_t *out);
+
 /* Bytes of device memory fcs_plan_bind needs for hash and twiddle tables. */
 FCS_API size_t fcs_plan_table_bytes(fcs_plan_t plan);
 
@@ -346,6 +362,24 @@ FCS_API fcs_status fcs_sketch_spectrum(fcs_plan_t plan, const float *y, float *s
 FCS_API fcs_status fcs_contract_inner(fcs_plan_t plan, const float *a, const float *b,
                               double *median, double *per_d, void *ws,
                               size_t ws_bytes, void *stream);
+
+/* The same for any D sketches of `len` entries each (a, b: D x len, e.g.
+ * tensor sketches from fcs_ts_fold); ws needs 8 D bytes (rounded up to 256)
+ * when per_d is NULL.  Errors: FCS_EINVAL, FCS_ENOMEM, FCS_EDEVICE. */
+FCS_API fcs_status fcs_inner_median(int32_t D, int64_t len, const float *a, const float *b,
+                            double *median, double *per_d, void *ws, size_t ws_bytes,
+                            void *stream);
+
+/* Tensor sketch of Definition 2 (the comparison sketch of Section 2.2)
+ * under the plan's hash pairs, from a fast count sketch y of the same tensor
+ * and plan: with every J_n = J the tensor sketch's bin is the fast count
+ * sketch's bin modulo J, so ts[d][k] = sum over m = k (mod J) of y[d][m]
+ * (Section 3, item 2).  Folds the sketch of any input (dense, COO, CP).
+ *   y   device, float, D x J~
+ *   ts  device, float, D x J; overwritten
+ * Errors: FCS_EINVAL (null pointers, unequal J_n, a higher-order count
+ * sketch plan), FCS_EDEVICE. */
+FCS_API fcs_status fcs_ts_fold(fcs_plan_t plan, const float *y, float *ts, void *stream);
 
 /* T(I, u, v)-type contraction, Section 4.1: the identity at mode
  * `free_mode` and a vector at every other mode.  For each sketch d and pair

@@ -41,6 +41,7 @@ class BatchConfig(ctypes.Structure):
 # (name, restype, argtypes); every entry point of include/fcs.h
 SIGNATURES = {
     "fcs_plan_create": (I32, [ctypes.POINTER(PlanDesc), ctypes.POINTER(P)]),
+    "fcs_plan_create_hcs": (I32, [ctypes.POINTER(PlanDesc), ctypes.POINTER(P)]),
     "fcs_plan_table_bytes": (SZ, [P]),
     "fcs_plan_bind": (I32, [P, P, P]),
     "fcs_plan_export": (I32, [P, I32, I32, P, P, P]),
@@ -67,6 +68,8 @@ SIGNATURES = {
     "fcs_batch_run": (I32, [P, P, SZ, I32, P]),
     "fcs_batch_destroy": (I32, [P]),
     "fcs_contract_inner": (I32, [P, P, P, P, P, P, SZ, P]),
+    "fcs_inner_median": (I32, [I32, I64, P, P, P, P, P, SZ, P]),
+    "fcs_ts_fold": (I32, [P, P, P, P]),
     "fcs_contract_free_mode": (I32, [P, P, I32, I64, ctypes.POINTER(P), P, P, SZ, P]),
     "fcs_contract_full": (I32, [P, P, I64, ctypes.POINTER(P), P, P, P, SZ, P]),
     "fcs_status_str": (ctypes.c_char_p, [I32]),

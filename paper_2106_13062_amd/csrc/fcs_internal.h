@@ -30,6 +30,13 @@ constexpr size_t FCS_LDS_BYTES = 160 * 1024;   // LDS per CU on gfx950
 struct fcs_plan {
     int N = 0, D = 0;
     int64_t I[FCS_MAX_ORDER] = {0}, J[FCS_MAX_ORDER] = {0};
+    // hash values: h_n(i) = hmul[n] * lemire(y, Jh[n]), so J[n] = (Jh[n] - 1)
+    // * hmul[n] + 1.  A sketch plan has hmul = 1 and Jh = J; a higher-order
+    // count sketch plan has the mixed-radix strides hmul[n] = prod_{m<n} Jh[m],
+    // so that sum_n h_n(i_n) is the flattened multi-index (mode 0 fastest)
+    // and J~ = prod_n Jh[n]
+    int64_t Jh[FCS_MAX_ORDER] = {0}, hmul[FCS_MAX_ORDER] = {0};
+    bool hcs = false;
     int64_t off[FCS_MAX_ORDER] = {0};   // offset of mode n inside a sketch's table
     int64_t sumI = 0;
     uint64_t seed = 0;

@@ -77,7 +77,8 @@ struct HashArgs {
     uint32_t *tab;
     uint64_t seed_mixed;   // mix(seed)
     int64_t off[FCS_MAX_ORDER + 1];
-    int64_t J[FCS_MAX_ORDER];
+    int64_t J[FCS_MAX_ORDER];      // hash range Jh_n of the multiply-shift
+    int64_t hmul[FCS_MAX_ORDER];   // multiplier of the hash values
     int N;
     int64_t sumI;
     int64_t total;         // D * sumI
@@ -93,7 +94,7 @@ __global__ void hash_tables_kernel(HashArgs a) {
     const int64_t i = e - a.off[n];
     const uint64_t key = sm64_mix(a.seed_mixed + ((uint64_t)d << 16) + (uint64_t)n);
     const uint64_t y = sm64_mix(key + (uint64_t)i);
-    const uint64_t h = ((y >> 32) * (uint64_t)a.J[n]) >> 32;
+    const uint64_t h = (((y >> 32) * (uint64_t)a.J[n]) >> 32) * (uint64_t)a.hmul[n];
     a.tab[t] = (uint32_t)h | ((y & 1ull) ? FCS_S_BIT : 0u);
 }
 
@@ -179,8 +180,7 @@ static bool choose_transform(fcs_plan *p, int64_t Lreq) {
     return found;
 }
 
-extern "C" fcs_status fcs_plan_create(const fcs_plan_desc *desc, fcs_plan_t *out) {
-    fcs_clear_error();
+static fcs_status plan_create(const fcs_plan_desc *desc, fcs_plan_t *out, bool hcs) {
     if (!desc || !out) FCS_FAIL(FCS_EINVAL, "null description or output pointer");
     if (desc->N < 1 || desc->N > FCS_MAX_ORDER)
         FCS_FAIL(FCS_EINVAL, "order N=%d outside [1, %d]", desc->N, FCS_MAX_ORDER);
@@ -199,13 +199,24 @@ extern "C" fcs_status fcs_plan_create(const fcs_plan_desc *desc, fcs_plan_t *out
         if (desc->I[n] > INT32_MAX) FCS_FAIL(FCS_EUNSUPPORTED, "I[%d] exceeds 2^31-1", n);
         if (desc->J[n] > INT32_MAX) FCS_FAIL(FCS_EUNSUPPORTED, "J[%d] exceeds 2^31-1", n);
         tmp.I[n] = desc->I[n];
-        tmp.J[n] = desc->J[n];
+        tmp.Jh[n] = desc->J[n];
         tmp.off[n] = tmp.sumI;
         tmp.sumI += desc->I[n];
         prodI *= (double)desc->I[n];
-        sumJ += desc->J[n];
     }
     if (prodI >= 4.6e18) FCS_FAIL(FCS_EUNSUPPORTED, "tensor has 2^62 or more entries");
+    tmp.hcs = hcs;
+    int64_t mul = 1;
+    for (int n = 0; n < tmp.N; ++n) {
+        tmp.hmul[n] = hcs ? mul : 1;
+        tmp.J[n] = (tmp.Jh[n] - 1) * tmp.hmul[n] + 1;
+        sumJ += tmp.J[n];
+        if (hcs) {
+            mul *= tmp.Jh[n];
+            if (mul >= ((int64_t)1 << 31) - 1)
+                FCS_FAIL(FCS_EUNSUPPORTED, "prod J_n exceeds 2^31 - 2 for a higher-order count sketch");
+        }
+    }
     tmp.Jt = sumJ - tmp.N + 1;
     if (tmp.Jt >= ((int64_t)1 << 31) - 1) FCS_FAIL(FCS_EUNSUPPORTED, "J~ = %lld too large", (long long)tmp.Jt);
     if (desc->L != 0) {
@@ -246,6 +257,16 @@ extern "C" fcs_status fcs_plan_create(const fcs_plan_desc *desc, fcs_plan_t *out
     return FCS_OK;
 }
 
+extern "C" fcs_status fcs_plan_create(const fcs_plan_desc *desc, fcs_plan_t *out) {
+    fcs_clear_error();
+    return plan_create(desc, out, false);
+}
+
+extern "C" fcs_status fcs_plan_create_hcs(const fcs_plan_desc *desc, fcs_plan_t *out) {
+    fcs_clear_error();
+    return plan_create(desc, out, true);
+}
+
 extern "C" size_t fcs_plan_table_bytes(fcs_plan_t p) { return p ? p->total : 0; }
 
 // Inverse hash lists (bucket offsets and entries per sketch and mode),
@@ -257,7 +278,7 @@ static fcs_status build_inverse(const fcs_plan *p, int32_t *dev_inv, hipStream_t
     for (int d = 0; d < p->D; ++d) {
         for (int n = 0; n < p->N; ++n) {
             int32_t *blk = host.data() + (size_t)d * p->iblock + p->ioff[n];
-            const int64_t In = p->I[n], Jn = p->J[n];
+            const int64_t In = p->I[n], Jn = p->J[n], Jh = p->Jh[n], hm = p->hmul[n];
             int32_t *off = blk;
             int32_t *ent = blk + Jn + 1;
             std::vector<uint32_t> word((size_t)In);
@@ -265,7 +286,7 @@ static fcs_status build_inverse(const fcs_plan *p, int32_t *dev_inv, hipStream_t
             for (int64_t j = 0; j <= Jn; ++j) off[j] = 0;
             for (int64_t i = 0; i < In; ++i) {
                 const uint64_t y = sm64_mix(key + (uint64_t)i);
-                const uint32_t h = (uint32_t)(((y >> 32) * (uint64_t)Jn) >> 32);
+                const uint32_t h = (uint32_t)((((y >> 32) * (uint64_t)Jh) >> 32) * (uint64_t)hm);
                 word[(size_t)i] = h | ((y & 1ull) ? FCS_S_BIT : 0u);
                 off[h + 1] += 1;
             }
@@ -307,7 +328,7 @@ void fcs_mode0_hashes(const fcs_plan *p, uint32_t *h0) {
         const uint64_t key = sm64_mix(sm + ((uint64_t)d << 16) + 0u);
         for (int64_t i = 0; i < p->I[0]; ++i) {
             const uint64_t y = sm64_mix(key + (uint64_t)i);
-            h0[(size_t)d * p->I[0] + i] = (uint32_t)(((y >> 32) * (uint64_t)p->J[0]) >> 32);
+            h0[(size_t)d * p->I[0] + i] = (uint32_t)((((y >> 32) * (uint64_t)p->Jh[0]) >> 32) * (uint64_t)p->hmul[0]);
         }
     }
 }
@@ -324,7 +345,7 @@ static int mode0_multiplicity(const fcs_plan *p) {
         const uint64_t key = sm64_mix(sm + ((uint64_t)d << 16) + 0u);
         for (int64_t i = 0; i < I0; ++i) {
             const uint64_t y = sm64_mix(key + (uint64_t)i);
-            h[(size_t)i] = (uint32_t)(((y >> 32) * (uint64_t)p->J[0]) >> 32);
+            h[(size_t)i] = (uint32_t)((((y >> 32) * (uint64_t)p->Jh[0]) >> 32) * (uint64_t)p->hmul[0]);
         }
         std::sort(h.begin(), h.end());
         int run = 1;
@@ -351,7 +372,10 @@ extern "C" fcs_status fcs_plan_bind(fcs_plan_t p, void *dev_tables, void *stream
     a.tab = (uint32_t *)(base + p->tab_off);
     a.seed_mixed = sm64_mix(p->seed);
     for (int n = 0; n < FCS_MAX_ORDER + 1; ++n) a.off[n] = (n < p->N) ? p->off[n] : p->sumI;
-    for (int n = 0; n < FCS_MAX_ORDER; ++n) a.J[n] = (n < p->N) ? p->J[n] : 1;
+    for (int n = 0; n < FCS_MAX_ORDER; ++n) {
+        a.J[n] = (n < p->N) ? p->Jh[n] : 1;
+        a.hmul[n] = (n < p->N) ? p->hmul[n] : 1;
+    }
     a.N = p->N;
     a.sumI = p->sumI;
     a.total = (int64_t)p->D * p->sumI;

@@ -42,8 +42,11 @@ class Plan:
     """A bound FCS plan: D sketches of an order-N tensor with mode sizes I and
     hash lengths J, hash pairs drawn from ``seed`` (see include/fcs.h)."""
 
-    def __init__(self, I, J, D: int, seed: int, L: int = 0, device=None, stream=None):
+    def __init__(self, I, J, D: int, seed: int, L: int = 0, device=None, stream=None, hcs: bool = False):
+        """hcs: a plan of the higher-order count sketch (Definition 3) with
+        the same hash pairs, its sketches flattened to prod(J) entries."""
         self.lib = C.load()
+        self.hcs = bool(hcs)
         self.I = tuple(int(i) for i in I)
         self.J = tuple(int(j) for j in J)
         self.N = len(self.I)
@@ -53,7 +56,8 @@ class Plan:
         Ja = (_I64 * self.N)(*self.J)
         desc = C.PlanDesc(self.N, Ia, Ja, self.D, self.seed, int(L))
         h = ctypes.c_void_p()
-        C.check(self.lib.fcs_plan_create(ctypes.byref(desc), ctypes.byref(h)))
+        create = self.lib.fcs_plan_create_hcs if self.hcs else self.lib.fcs_plan_create
+        C.check(create(ctypes.byref(desc), ctypes.byref(h)))
         self._h = h
         Jt, Lt, Pt, Qt = _I64(), _I64(), _I64(), ctypes.c_int32()
         C.check(self.lib.fcs_plan_info(h, ctypes.byref(Jt), ctypes.byref(Lt), ctypes.byref(Pt),
@@ -253,6 +257,17 @@ class Plan:
                                             _stream(stream)))
         return med, per_d
 
+    def ts_fold(self, y: torch.Tensor, out=None, stream=None) -> torch.Tensor:
+        """Tensor sketch (Definition 2, all J_n equal) of the tensor whose
+        fast count sketches under this plan are y (D x J~): D x J."""
+        _need(y, torch.float32, "y")
+        if tuple(y.shape) != (self.D, self.Jt):
+            raise ValueError("y must be D x J~")
+        out = torch.empty((self.D, self.J[0]), dtype=torch.float32, device=self.device) if out is None else out
+        _need(out, torch.float32, "out")
+        C.check(self.lib.fcs_ts_fold(self._h, _ptr(y), _ptr(out), _stream(stream)))
+        return out
+
     def contract_free_mode(self, spec: torch.Tensor, free_mode: int, vecs, out=None, ws=None, stream=None):
         """vecs: list of N entries; vecs[free_mode] is ignored (may be None);
         the others are float32 P x I_n."""
@@ -395,3 +410,18 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def inner_median(a: torch.Tensor, b: torch.Tensor, stream=None):
+    """fcs_inner_median: per-row inner products of two D x len float32
+    tensors (double) and their median, e.g. for tensor sketches."""
+    lib = C.load()
+    _need(a, torch.float32, "a")
+    _need(b, torch.float32, "b")
+    if a.dim() != 2 or a.shape != b.shape:
+        raise ValueError("a and b must be D x len of equal shape")
+    D, n = int(a.shape[0]), int(a.shape[1])
+    med = torch.empty(1, dtype=torch.float64, device=a.device)
+    per_d = torch.empty(D, dtype=torch.float64, device=a.device)
+    C.check(lib.fcs_inner_median(D, n, _ptr(a), _ptr(b), _ptr(med), _ptr(per_d), None, 0, _stream(stream)))
+    return med, per_d

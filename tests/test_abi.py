@@ -116,3 +116,33 @@ def test_status_strings():
     lib = F.load()
     for code in range(6):
         assert lib.fcs_status_str(code)
+
+
+def test_hcs_plan_sizes():
+    """A higher-order count sketch plan flattens J_0 x ... x J_{N-1}: J~ is
+    the product of the hash lengths; products beyond the 31-bit range are
+    refused before any device work."""
+    lib = F.load()
+    I, J = [50, 40, 30], [14, 9, 5]
+    Ia = (ctypes.c_int64 * 3)(*I)
+    Ja = (ctypes.c_int64 * 3)(*J)
+    h = ctypes.c_void_p()
+    assert lib.fcs_plan_create_hcs(ctypes.byref(L.PlanDesc(3, Ia, Ja, 2, 7, 0)), ctypes.byref(h)) == 0
+    Jt = ctypes.c_int64()
+    lib.fcs_plan_info(h, ctypes.byref(Jt), None, None, None)
+    assert Jt.value == 14 * 9 * 5
+    lib.fcs_plan_destroy(h)
+    Jb = (ctypes.c_int64 * 3)(*[2048, 2048, 1024])
+    assert lib.fcs_plan_create_hcs(ctypes.byref(L.PlanDesc(3, Ia, Jb, 2, 7, 0)), ctypes.byref(h)) == \
+        L.FCS_EUNSUPPORTED
+
+
+def test_ts_fold_and_inner_median_validate_before_device_work():
+    lib = F.load()
+    st, h = _create(2, [8, 8], [4, 5], 2)
+    x = ctypes.c_void_p(16)
+    assert lib.fcs_ts_fold(h, x, x, None) == L.FCS_EINVAL        # unequal hash lengths
+    assert lib.fcs_inner_median(0, 10, x, x, x, None, None, 0, None) == L.FCS_EINVAL
+    assert lib.fcs_inner_median(2, 0, x, x, x, None, None, 0, None) == L.FCS_EINVAL
+    assert lib.fcs_inner_median(2, 10, x, x, x, None, None, 0, None) == L.FCS_EINVAL   # no workspace
+    lib.fcs_plan_destroy(h)

@@ -1,0 +1,198 @@
+"""GPU parity of the comparison sketches of Section 2.2 computed on the same
+hash pairs as FCS: the higher-order count sketch (Definition 3) through an
+HCS plan (mode hashes scaled by the mixed-radix strides, so that the FCS
+kernels produce the flattened HCS), the tensor sketch (Definition 2) as the
+fold of FCS modulo J, and the inner-product medians of both, against the
+FP64 oracle's definitions (hcs_dense, hcs_cp, hcs_decompress_median,
+ts_dense, ts_cp).  Bars: hash words and decompression bit-exact, integer
+data bit-exact, float sketches within relative L2 error 1e-5."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synth
+from paper_2106_13062_amd import Plan, inner_median
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+TOL = 1e-5
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / nb) if nb > 0 else float(np.linalg.norm(a))
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+def strides(J):
+    return [int(x) for x in np.cumprod([1] + list(J[:-1]))]
+
+
+HCS_CASES = [
+    # (I, J, D): per-mode HCS hash lengths
+    ((50, 50, 50), (20, 20, 20), 3),        # the 50^3 power-method shape at J = 20
+    ((64, 33, 17), (14, 9, 5), 5),
+    ((100, 80), (64, 32), 2),
+    ((30, 20, 10, 6), (5, 4, 3, 2), 4),
+    ((1000,), (97,), 2),                    # order 1: a count sketch
+]
+
+
+@pytest.mark.parametrize("I,J,D", HCS_CASES)
+def test_hcs_plan_hashes_are_scaled_fcs_hashes(I, J, D):
+    seed = 61
+    plan = Plan(I, J, D, seed, device=DEV, hcs=True)
+    assert plan.Jt == int(np.prod(J))
+    hs, ss = O.hash_tables(seed, D, I, J)
+    st = strides(J)
+    for d in range(D):
+        for n in range(len(I)):
+            h, s = plan.export(d, n)
+            assert np.array_equal(h.astype(np.int64), hs[d][n] * st[n]), (d, n)
+            assert np.array_equal(s, ss[d][n]), (d, n)
+
+
+@pytest.mark.parametrize("I,J,D", HCS_CASES)
+def test_hcs_dense_matches_definition_3(I, J, D):
+    print(f"hcs dense I={I} J={J} D={D}", flush=True)
+    seed = 62
+    plan = Plan(I, J, D, seed, device=DEV, hcs=True)
+    hs, ss = O.hash_tables(seed, D, I, J)
+    T = synth.dense_tensor(8, I).reshape(I[::-1]).transpose()    # array indexed (i_0, ..., i_{N-1})
+    got = plan.sketch_dense(dev(O.vec(T).astype(np.float32))).cpu().numpy()
+    for d in range(D):
+        want = O.vec(O.hcs_dense(T, hs[d], ss[d], J))
+        assert rel(got[d], want) <= TOL, (d, rel(got[d], want))
+    Ti = synth.integer_tensor(9, I, -2, 2).reshape(I[::-1]).transpose()
+    got = plan.sketch_dense(dev(O.vec(Ti).astype(np.float32))).cpu().numpy()
+    for d in range(D):
+        assert np.array_equal(got[d].astype(np.float64), O.vec(O.hcs_dense(Ti, hs[d], ss[d], J)))
+
+
+@pytest.mark.parametrize("I,J,R,D", [((50, 50, 50), (20, 20, 20), 10, 3), ((64, 33, 17), (14, 9, 5), 7, 2),
+                                     ((30, 20, 10, 6), (5, 4, 3, 2), 3, 2)])
+def test_hcs_cp_matches_rank_one_form(I, J, R, D):
+    print(f"hcs cp I={I} J={J} R={R} D={D}", flush=True)
+    seed = 63
+    U = synth.cp_factors(11, I, R)
+    lam = synth.rng(12).standard_normal(R).astype(np.float32)
+    plan = Plan(I, J, D, seed, device=DEV, hcs=True)
+    y, _ = plan.sketch_cp([dev(u.T) for u in U], lam=dev(lam))
+    y = y.cpu().numpy()
+    hs, ss = O.hash_tables(seed, D, I, J)
+    for d in range(D):
+        want = O.vec(O.hcs_cp(lam, U, hs[d], ss[d], J))
+        assert rel(y[d], want) <= TOL, (d, rel(y[d], want))
+
+
+def test_hcs_coo_matches_dense_definition():
+    I, J, D, seed = (40, 30, 20), (9, 8, 7), 3, 64
+    T = synth.dense_tensor(13, I)
+    idx, val = synth.bernoulli_coo(13, T, I, 0.3)
+    plan = Plan(I, J, D, seed, device=DEV, hcs=True)
+    got = plan.sketch_coo(dev(idx), dev(val)).cpu().numpy()
+    hs, ss = O.hash_tables(seed, D, I, J)
+    dense = np.zeros(int(np.prod(I)), dtype=np.float64)
+    lin = idx[0].astype(np.int64) + I[0] * (idx[1].astype(np.int64) + I[1] * idx[2].astype(np.int64))
+    dense[lin] = val
+    Td = dense.reshape(I[::-1]).transpose()
+    for d in range(D):
+        want = O.vec(O.hcs_dense(Td, hs[d], ss[d], J))
+        assert rel(got[d], want) <= TOL, (d, rel(got[d], want))
+
+
+@pytest.mark.parametrize("I,J,D", [((12, 10, 9), (5, 4, 3), 3), ((8, 7, 6, 5), (3, 3, 2, 2), 4), ((16, 15), (6, 5), 5)])
+def test_hcs_decompress_is_bit_exact(I, J, D):
+    seed = 65
+    plan = Plan(I, J, D, seed, device=DEV, hcs=True)
+    hs, ss = O.hash_tables(seed, D, I, J)
+    Y = np.random.default_rng(D).standard_normal((D, int(np.prod(J)))).astype(np.float32)
+    got = plan.decompress(dev(Y)).cpu().numpy()
+    Yt = [Y[d].astype(np.float64).reshape(J[::-1]).transpose() for d in range(D)]
+    want = O.vec(O.hcs_decompress_median(Yt, hs, ss, I)).astype(np.float32)
+    np.testing.assert_array_equal(got, want)
+
+
+TS_CASES = [((50, 50, 50), 300, 4), ((400, 40, 30), 3000, 3), ((33, 21, 17, 9), 64, 2), ((500,), 97, 3)]
+
+
+@pytest.mark.parametrize("I,J,D", TS_CASES)
+def test_ts_fold_matches_definition_2(I, J, D):
+    print(f"ts I={I} J={J} D={D}", flush=True)
+    seed = 66
+    Js = (J,) * len(I)
+    plan = Plan(I, Js, D, seed, device=DEV)
+    hs, ss = O.hash_tables(seed, D, I, Js)
+    T = synth.dense_tensor(14, I).reshape(I[::-1]).transpose()
+    ts = plan.ts_fold(plan.sketch_dense(dev(O.vec(T).astype(np.float32)))).cpu().numpy()
+    for d in range(D):
+        want = O.ts_dense(T, hs[d], ss[d], J)
+        assert rel(ts[d], want) <= TOL, (d, rel(ts[d], want))
+    # CP input: the fold of the FFT-path FCS is the circular-convolution TS
+    R = 5
+    U = synth.cp_factors(15, I, R)
+    y, _ = plan.sketch_cp([dev(u.T) for u in U])
+    ts = plan.ts_fold(y).cpu().numpy()
+    for d in range(D):
+        want = O.ts_cp(None, U, hs[d], ss[d], J)
+        assert rel(ts[d], want) <= TOL, (d, rel(ts[d], want))
+
+
+def test_ts_fold_rejects_unequal_hash_lengths_and_hcs_plans():
+    from paper_2106_13062_amd import FcsError
+    p = Plan((5, 6), (4, 5), 2, 1, device=DEV)
+    with pytest.raises(FcsError):
+        p.ts_fold(torch.zeros((2, p.Jt), device=DEV))
+    h = Plan((5, 6), (4, 4), 2, 1, device=DEV, hcs=True)
+    with pytest.raises(FcsError):
+        h.ts_fold(torch.zeros((2, h.Jt), device=DEV))
+
+
+def test_inner_medians_of_ts_and_hcs_sketches():
+    """Proposition 1's inner products for the comparison sketches, through
+    fcs_inner_median (TS, length J) and fcs_contract_inner (HCS plan)."""
+    I, D, seed = (30, 25, 20), 5, 67
+    M = synth.dense_tensor(16, I)
+    Nt = (M + 0.5 * synth.dense_tensor(17, I)).astype(np.float32)
+    ts_plan = Plan(I, (64, 64, 64), D, seed, device=DEV)
+    a = ts_plan.ts_fold(ts_plan.sketch_dense(dev(M)))
+    b = ts_plan.ts_fold(ts_plan.sketch_dense(dev(Nt)))
+    med, per_d = inner_median(a, b)
+    w_med, w_per = O.inner_median(a.cpu().numpy(), b.cpu().numpy())
+    scale = np.linalg.norm(a.cpu().numpy().astype(np.float64), axis=1) * np.linalg.norm(
+        b.cpu().numpy().astype(np.float64), axis=1)
+    assert np.all(np.abs(per_d.cpu().numpy() - w_per) <= 1e-12 * scale)
+    assert abs(float(med.cpu()[0]) - w_med) <= 1e-12 * scale.max()
+    hplan = Plan(I, (8, 8, 8), D, seed, device=DEV, hcs=True)
+    ya, yb = hplan.sketch_dense(dev(M)), hplan.sketch_dense(dev(Nt))
+    med, per_d = hplan.contract_inner(ya, yb)
+    w_med, w_per = O.inner_median(ya.cpu().numpy(), yb.cpu().numpy())
+    assert abs(float(med.cpu()[0]) - w_med) <= 1e-9 * max(1.0, abs(w_med))
+
+
+def test_sketched_inner_products_are_unbiased_over_seeds():
+    """Proposition 1 consistency on the device: over many independent hash
+    draws the mean FCS, TS and HCS inner-product estimates of <M, N> sit
+    within 5 standard errors of the exact value."""
+    I = (12, 10, 8)
+    M = synth.dense_tensor(18, I)
+    Nt = (M + synth.dense_tensor(19, I)).astype(np.float32)
+    exact = float(np.dot(M.astype(np.float64), Nt.astype(np.float64)))
+    Md, Nd = dev(M), dev(Nt)
+    est = {"fcs": [], "ts": [], "hcs": []}
+    for seed in range(300):
+        p = Plan(I, (16, 16, 16), 1, 5000 + seed, device=DEV)
+        ya, yb = p.sketch_dense(Md), p.sketch_dense(Nd)
+        est["fcs"].append(float(p.contract_inner(ya, yb)[0].cpu()[0]))
+        est["ts"].append(float(inner_median(p.ts_fold(ya), p.ts_fold(yb))[0].cpu()[0]))
+        h = Plan(I, (4, 4, 3), 1, 5000 + seed, device=DEV, hcs=True)
+        est["hcs"].append(float(h.contract_inner(h.sketch_dense(Md), h.sketch_dense(Nd))[0].cpu()[0]))
+    for k, v in est.items():
+        v = np.asarray(v)
+        assert abs(v.mean() - exact) <= 5 * v.std(ddof=1) / np.sqrt(v.size), (k, v.mean(), exact)
