@@ -738,6 +738,144 @@ def copy_calibration(torch, dev, nbytes=1 << 30, reps=5):
     print(json.dumps({"copy_bytes": nbytes, "reps": reps}), flush=True)
 
 
+def _recovery_error(torch, got, want):
+    return float(torch.linalg.norm(got.double() - want.double()) / torch.linalg.norm(want.double()))
+
+
+def compare_workload(args, torch, dev):
+    """The paper's Kronecker and contraction compression experiments (Section
+    4.3) with FCS against the long-hash count sketch (CS: Definition 1 on
+    vec(T), an order-1 plan over all prod I_n entries) and the higher-order
+    count sketch (HCS: Definition 3, an HCS plan with the same per-mode hash
+    pairs), D = 20, at compression ratios CR = prod I_n / J~ (HCS: per-mode
+    hash length round(J~^(1/4))).  Kronecker: A 30 x 40 and B 40 x 50, U[-5, 5];
+    contraction: A 30 x 40 x 50 and B 50 x 40 x 30, U[0, 10], over the shared
+    index.  Per method: compression and decompression time (HIP events),
+    relative error of the recovered tensor, hash-function memory (the packed
+    (h, s) words, 4 B per index and sketch) and the bound plan's table
+    bytes.  FCS compresses from the factors; CS and HCS compress the
+    materialised tensor, whose construction (torch, on the device) is timed
+    apart.  Also Proposition 1's variance comparison under equal hash
+    functions: inner-product estimates of FCS, TS (the mod-J fold of the
+    same sketches) and HCS over many independent hash draws."""
+    import synth
+    from paper_2106_13062_amd import Plan, inner_median
+    stream = torch.cuda.current_stream()
+    g = synth.rng(synth.DATA_SEED["batch4096"], 41)
+    D = 20
+    reps = max(3, args.steps // 4)
+    out = {}
+
+    def methods(name, I, make_full, fcs_compress, crs):
+        n = int(np.prod(I))
+        full = make_full()
+        t_mat, _ = event_timer(torch, stream, make_full, reps)
+        rows = []
+        for cr in crs:
+            Jt = n // cr
+            row = {"CR": cr, "Jt_target": Jt}
+            J = (Jt + 3) // 4
+            try:
+                pf = Plan(I, (J,) * 4, D, 91, device=dev)
+            except Exception as e:          # no transform length fits
+                pf = None
+                row["fcs"] = {"error": str(e)}
+            if pf is not None:
+                y = fcs_compress(pf)
+                c_ms, _ = event_timer(torch, stream, lambda: fcs_compress(pf), reps)
+                rec = pf.decompress(y)
+                d_ms, _ = event_timer(torch, stream, lambda: pf.decompress(y, out=rec, stream=stream), reps)
+                row["fcs"] = {"J": J, "Jt": pf.Jt, "compress_ms": c_ms, "decompress_ms": d_ms,
+                              "rel_error": _recovery_error(torch, rec, full),
+                              "hash_bytes": 4 * D * sum(I), "plan_table_bytes": int(pf.tables.numel())}
+                pf.close()
+            pc = Plan((n,), (Jt,), D, 92, device=dev)
+            wsc = pc.workspace(0)
+            y = pc.sketch_dense(full, ws=wsc)
+            c_ms, _ = event_timer(torch, stream, lambda: pc.sketch_dense(full, out=y, ws=wsc, stream=stream), reps)
+            rec = pc.decompress(y)
+            d_ms, _ = event_timer(torch, stream, lambda: pc.decompress(y, out=rec, stream=stream), reps)
+            row["cs"] = {"Jt": pc.Jt, "compress_ms": c_ms, "compress_with_materialise_ms": c_ms + t_mat,
+                         "decompress_ms": d_ms, "rel_error": _recovery_error(torch, rec, full),
+                         "hash_bytes": 4 * D * n, "plan_table_bytes": int(pc.tables.numel())}
+            pc.close()
+            Jh = max(1, int(round(Jt ** 0.25)))
+            ph = Plan(I, (Jh,) * 4, D, 93, device=dev, hcs=True)
+            wsh = ph.workspace(0)
+            y = ph.sketch_dense(full, ws=wsh)
+            c_ms, _ = event_timer(torch, stream, lambda: ph.sketch_dense(full, out=y, ws=wsh, stream=stream), reps)
+            rec = ph.decompress(y)
+            d_ms, _ = event_timer(torch, stream, lambda: ph.decompress(y, out=rec, stream=stream), reps)
+            row["hcs"] = {"J": Jh, "Jt": ph.Jt, "compress_ms": c_ms, "compress_with_materialise_ms": c_ms + t_mat,
+                          "decompress_ms": d_ms, "rel_error": _recovery_error(torch, rec, full),
+                          "hash_bytes": 4 * D * sum(I), "plan_table_bytes": int(ph.tables.numel())}
+            ph.close()
+            if "hash_bytes" in row.get("fcs", {}):
+                row["fcs_hash_memory_vs_cs"] = row["fcs"]["hash_bytes"] / row["cs"]["hash_bytes"]
+            rows.append(row)
+            torch.cuda.empty_cache()
+        out[name] = {"I": list(I), "entries": n, "materialise_ms": t_mat, "rows": rows}
+
+    # Kronecker product A (x) B as the order-4 tensor T[a, b, c, d] = A[a, b] B[c, d]
+    A = torch.from_numpy(g.uniform(-5, 5, (30, 40)).astype(np.float32)).to(dev)
+    B = torch.from_numpy(g.uniform(-5, 5, (40, 50)).astype(np.float32)).to(dev)
+    Ak, Bk = A.t().contiguous(), B.t().contiguous()          # column-major matrices
+    wsk = {}
+
+    def kron_fcs(p):
+        if p.Jt not in wsk:
+            wsk[p.Jt] = p.workspace(6)
+        return p.sketch_kron(Ak, Bk, ws=wsk[p.Jt], stream=stream)[0]
+
+    methods("kron_30x40_40x50", (30, 40, 40, 50),
+            lambda: torch.einsum("ab,cd->dcba", A, B).contiguous().reshape(-1), kron_fcs, (4, 8, 16, 32, 64))
+    wsk.clear()
+    # contraction C[a, b, c, d] = sum_l A[a, b, l] B[l, c, d]
+    Ac = torch.from_numpy(g.uniform(0, 10, (30, 40, 50)).astype(np.float32)).to(dev)
+    Bc = torch.from_numpy(g.uniform(0, 10, (50, 40, 30)).astype(np.float32)).to(dev)
+    Acm = Ac.permute(2, 1, 0).contiguous().reshape(-1)       # column-major (a fastest)
+    Bcm = Bc.permute(2, 1, 0).contiguous().reshape(-1)       # column-major (l fastest)
+    wsc = {}
+
+    def contraction_fcs(p):
+        if p.Jt not in wsc:
+            wsc[p.Jt] = p.workspace(7, R=50)
+        return p.sketch_contraction(Acm, Bcm, ws=wsc[p.Jt], stream=stream)[0]
+
+    methods("contraction_30x40x50_50x40x30", (30, 40, 40, 30),
+            lambda: torch.einsum("abl,lcd->dcba", Ac, Bc).contiguous().reshape(-1), contraction_fcs,
+            (4, 8, 16, 32, 64))
+    wsc.clear()
+    torch.cuda.empty_cache()
+
+    # Proposition 1: variance of the inner-product estimate under equal hash
+    # functions, FCS (J~ = 3J - 2 bins) against TS (its fold modulo J) and
+    # HCS (per-mode length round((3J - 2)^(1/3))), one sketch per hash draw
+    I, J, K = (30, 30, 30), 64, 2000
+    M = synth.dense_tensor(50, I)
+    Nn = (M + synth.dense_tensor(51, I)).astype(np.float32)
+    exact = float(np.dot(M.astype(np.float64), Nn.astype(np.float64)))
+    Md, Nd = torch.from_numpy(M).to(dev), torch.from_numpy(Nn).to(dev)
+    Jh = int(round((3 * J - 2) ** (1.0 / 3.0)))
+    est = {"fcs": [], "ts": [], "hcs": []}
+    for k in range(K):
+        p = Plan(I, (J,) * 3, 1, 10_000 + k, device=dev)
+        ya, yb = p.sketch_dense(Md), p.sketch_dense(Nd)
+        est["fcs"].append(p.contract_inner(ya, yb)[0])
+        est["ts"].append(inner_median(p.ts_fold(ya), p.ts_fold(yb))[0])
+        h = Plan(I, (Jh,) * 3, 1, 10_000 + k, device=dev, hcs=True)
+        est["hcs"].append(h.contract_inner(h.sketch_dense(Md), h.sketch_dense(Nd))[0])
+    prop1 = {"I": list(I), "J": J, "hcs_J": Jh, "draws": K, "exact": exact,
+             "norm_M_norm_N": float(np.linalg.norm(M) * np.linalg.norm(Nn))}
+    for k_, v in est.items():
+        v = torch.cat(v).cpu().numpy()
+        prop1[k_] = {"mean": float(v.mean()), "var": float(v.var(ddof=1)),
+                     "mean_within_5_std_err": bool(abs(v.mean() - exact) <= 5 * v.std(ddof=1) / np.sqrt(K))}
+    prop1["var_fcs_over_var_ts"] = prop1["fcs"]["var"] / prop1["ts"]["var"]
+    out["prop1_variance"] = prop1
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -747,7 +885,8 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=1 << 19,
                     help="rows of the tensor the CPU oracle sketches")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "dense1024_traffic.json"))
-    ap.add_argument("--mode", default="full", choices=["full", "dense", "coo", "cp", "batch", "serve", "rtpm", "als", "decompress", "copy"],
+    ap.add_argument("--mode", default="full", choices=["full", "dense", "coo", "cp", "batch", "serve", "rtpm", "als", "decompress", "compare",
+                                                       "copy"],
                     help="full: headline + secondary workloads; dense: headline only; cp: the CP "
                          "sketches and T(I,u,v) only; batch: the uneven batch only; serve: the "
                          "serving loop only; copy: plain copy kernel for counter calibration")
@@ -798,6 +937,9 @@ def main():
     if args.mode == "decompress":
         print(json.dumps({"decompress": decompress_workload(args, torch, dev)}), flush=True)
         return
+    if args.mode == "compare":
+        print(json.dumps({"compare": compare_workload(args, torch, dev)}), flush=True)
+        return
     if args.mode == "cp":
         import synth
         print(json.dumps({"cp100": cp_workload(args, torch, dev, synth.CP100, inner=True),
@@ -830,6 +972,9 @@ def main():
         torch.cuda.empty_cache()
         log("secondary: decompression and contraction compression")
         secondary["decompress"] = decompress_workload(args, torch, dev)
+        torch.cuda.empty_cache()
+        log("secondary: CS / HCS / FCS comparison and Proposition 1 variances")
+        secondary["compare"] = compare_workload(args, torch, dev)
     del T
     # HBM traffic per launch from the committed FETCH_SIZE / WRITE_SIZE
     # summary, only while the kernel source is the one that was measured

@@ -428,15 +428,32 @@ size_t fcs_ws_cp(const fcs_plan *p, int64_t R) {
     return std::max<size_t>(256, cp_partial_bytes(p, nch) + cp_ytmp_bytes(p));
 }
 
+// factor sketches of a Kronecker or contraction plan whose 64-bit bins do
+// not fit LDS are summed in global memory (after the float sketches in the
+// workspace)
+static bool factor_bins_in_lds(const fcs_plan *p) {
+    const size_t nb = (size_t)std::max<int64_t>(p->J[0] + p->J[1] - 1, p->J[2] + p->J[3] - 1);
+    return nb * 8 <= FCS_LDS_BYTES - 1024;
+}
+
+static size_t factor_float_bytes(const fcs_plan *p, int64_t pairs) {
+    return align256((size_t)p->D * (size_t)pairs * (p->J[0] + p->J[1] - 1 + p->J[2] + p->J[3] - 1) * sizeof(float));
+}
+
+static size_t factor_bin_bytes(const fcs_plan *p, int64_t pairs) {
+    if (factor_bins_in_lds(p)) return 0;
+    return align256((size_t)p->D * (size_t)pairs * (p->J[0] + p->J[1] - 1 + p->J[2] + p->J[3] - 1) * 8);
+}
+
 size_t fcs_ws_kron(const fcs_plan *p) {
     if (p->N != 4) return 256;
-    return align256((size_t)p->D * (p->J[0] + p->J[1] - 1 + p->J[2] + p->J[3] - 1) * sizeof(float));
+    return factor_float_bytes(p, 1) + factor_bin_bytes(p, 1);
 }
 
 // contraction workspace: slice sketches, then the CP chunk partials and
 // slice terms for chunks of the shared index
 static size_t contraction_factor_bytes(const fcs_plan *p, int64_t Lc) {
-    return align256((size_t)p->D * (size_t)Lc * (p->J[0] + p->J[1] - 1 + p->J[2] + p->J[3] - 1) * sizeof(float));
+    return factor_float_bytes(p, Lc) + factor_bin_bytes(p, Lc);
 }
 
 size_t fcs_ws_contraction(const fcs_plan *p, int64_t Lc) {
@@ -585,9 +602,6 @@ extern "C" fcs_status fcs_sketch_kron(fcs_plan_t p, const float *A, const float 
     CpDesc c{};
     desc_from_plan(c, p);
     c.kind = FCS_DESC_KRON;
-    if (cp_lds_bytes((int)p->P, c) > FCS_LDS_BYTES - 1024)
-        FCS_FAIL(FCS_EUNSUPPORTED, "factor sketches of %d and %d bins exceed LDS", c.J[0] + c.J[1] - 1,
-                 c.J[2] + c.J[3] - 1);
     const size_t need = fcs_ws_kron(p);
     if (!ws || ws_bytes < need) FCS_FAIL(FCS_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, need);
     if (!fcs_aligned(ws, 16)) FCS_FAIL(FCS_EINVAL, "workspace not 16-byte aligned");
@@ -597,6 +611,8 @@ extern "C" fcs_status fcs_sketch_kron(fcs_plan_t p, const float *A, const float 
     c.nchunks = 1;
     c.rchunk = 1;
     c.kscratch = (float *)ws;
+    c.kbins = factor_bins_in_lds(p) ? nullptr
+                                    : reinterpret_cast<unsigned long long *>((char *)ws + factor_float_bytes(p, 1));
     c.out = out;
     c.spec = (float2 *)spec;
     hipStream_t s = (hipStream_t)stream;
@@ -617,9 +633,6 @@ extern "C" fcs_status fcs_sketch_contraction(fcs_plan_t p, int64_t Lc, const flo
     CpDesc c{};
     desc_from_plan(c, p);
     c.kind = FCS_DESC_CONTRACTION;
-    if (cp_lds_bytes((int)p->P, c) > FCS_LDS_BYTES - 1024)
-        FCS_FAIL(FCS_EUNSUPPORTED, "factor sketches of %d and %d bins exceed LDS", c.J[0] + c.J[1] - 1,
-                 c.J[2] + c.J[3] - 1);
     const size_t need = fcs_ws_contraction(p, Lc);
     if (!ws || ws_bytes < need) FCS_FAIL(FCS_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, need);
     if (!fcs_aligned(ws, 16)) FCS_FAIL(FCS_EINVAL, "workspace not 16-byte aligned");
@@ -629,6 +642,8 @@ extern "C" fcs_status fcs_sketch_contraction(fcs_plan_t p, int64_t Lc, const flo
     c.nchunks = cp_chunks(p, Lc);
     c.rchunk = (int)fcs_ceil_div(Lc, c.nchunks);
     c.kscratch = (float *)ws;
+    c.kbins = factor_bins_in_lds(p) ? nullptr
+                                    : reinterpret_cast<unsigned long long *>((char *)ws + factor_float_bytes(p, Lc));
     c.partial = (float2 *)((char *)ws + contraction_factor_bytes(p, Lc));
     c.ytmp = (float *)((char *)c.partial + cp_partial_bytes(p, c.nchunks));
     c.out = out;

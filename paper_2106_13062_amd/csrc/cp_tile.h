@@ -285,6 +285,8 @@ struct CpDesc {
                                      // rank chunks are chunks of the shared index
     float *out;                      // D x Jt or null
     float2 *spec;                    // D x (Qh * P) or null
+    unsigned long long *kbins;       // KRON / CONTRACTION: 64-bit factor-sketch bins in global memory, laid
+                                     // out like kscratch, when they exceed LDS (null: bins in LDS)
     int cnt_slice;                   // batch: first (d, q) chunk counter (nchunks > 1)
     int cnt_sketch;                  // batch: first per-d slice counter (Qh > 1)
 };
@@ -423,16 +425,19 @@ __device__ __forceinline__ void sum_slices(const CpDesc &c, int d) {
 // B = min(40, 62 - ceil(log2(I_a I_b))), so no bin can overflow and rounding
 // moves each entry by at most 2^-B of that largest magnitude (relative error
 // of the sketch at most sqrt(I_a I_b) 2^-B, below 1e-7 up to 2^20 entries).
-// lds must hold nb 64-bit words.  A matrix with a non-finite entry gives NaN
-// bins.
+// The nb 64-bit bins are in LDS (lds must hold them), or in global memory
+// at gbins when that is given (sketches too long for LDS; the bins are then
+// read back with device-scope loads, past the L1 cache).  A matrix with a
+// non-finite entry gives NaN bins.
 // With STRIDED, entry k of the matrix is M[k * stride] (a slice of a
 // larger tensor whose other index varies fastest).
 template <int T, bool STRIDED = false>
 __device__ __forceinline__ void kron_factor_sketch(const float *__restrict__ M, int Ia, int Ib,
                                                    const uint32_t *__restrict__ ta,
                                                    const uint32_t *__restrict__ tb, int nb, float *y,
-                                                   float2 *lds, int64_t stride = 1) {
-    unsigned long long *bins = reinterpret_cast<unsigned long long *>(lds);
+                                                   float2 *lds, int64_t stride = 1,
+                                                   unsigned long long *gbins = nullptr) {
+    unsigned long long *bins = gbins ? gbins : reinterpret_cast<unsigned long long *>(lds);
     float *red = reinterpret_cast<float *>(lds);
     const int t = tid_opaque();
     const int64_t n = (int64_t)Ia * Ib;
@@ -472,6 +477,7 @@ __device__ __forceinline__ void kron_factor_sketch(const float *__restrict__ M, 
     F = max(-120, min(127, F));
     const float scale = ldexpf(1.0f, F);
     for (int j = t; j < nb; j += T) bins[j] = 0ull;
+    if (gbins) __threadfence();
     __syncthreads();
     int i = t % Ia, j = t / Ia;
     const int st_i = T % Ia, st_j = T / Ia;
@@ -488,10 +494,15 @@ __device__ __forceinline__ void kron_factor_sketch(const float *__restrict__ M, 
             ++j;
         }
     }
+    if (gbins) __threadfence();
     __syncthreads();
     // 2^-F in two normal factors (F may reach 127)
     const float inv1 = ldexpf(1.0f, -(F / 2)), inv2 = ldexpf(1.0f, -(F - F / 2));
-    for (int b = t; b < nb; b += T) y[b] = (float)(long long)bins[b] * inv1 * inv2;
+    for (int b = t; b < nb; b += T) {
+        const unsigned long long v =
+            gbins ? __hip_atomic_load(&bins[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : bins[b];
+        y[b] = (float)(long long)v * inv1 * inv2;
+    }
     __syncthreads();
 }
 
@@ -507,8 +518,10 @@ __device__ __forceinline__ void kron_sketch(const CpDesc &c, int d, float2 *lds)
     const int nbb = c.J[2] + c.J[3] - 1;
     float *ya = c.kscratch + (int64_t)d * (na + nbb);
     float *yb = ya + na;
-    kron_factor_sketch<T>(c.U[0], c.I[0], c.I[1], tab + c.off[0], tab + c.off[1], na, ya, lds);
-    kron_factor_sketch<T>(c.U[1], c.I[2], c.I[3], tab + c.off[2], tab + c.off[3], nbb, yb, lds);
+    unsigned long long *ga = c.kbins ? c.kbins + (int64_t)d * (na + nbb) : nullptr;
+    kron_factor_sketch<T>(c.U[0], c.I[0], c.I[1], tab + c.off[0], tab + c.off[1], na, ya, lds, 1, ga);
+    kron_factor_sketch<T>(c.U[1], c.I[2], c.I[3], tab + c.off[2], tab + c.off[3], nbb, yb, lds, 1,
+                          ga ? ga + na : nullptr);
     __threadfence_block();
     __syncthreads();
     for (int q = 0; q < c.s.Qh; ++q) {
@@ -539,10 +552,11 @@ __device__ __forceinline__ void contraction_factors(const CpDesc &c, int d, int 
     const int na = c.J[0] + c.J[1] - 1;
     const int nbb = c.J[2] + c.J[3] - 1;
     float *ya = c.kscratch + ((int64_t)d * c.R + l) * (na + nbb);
+    unsigned long long *ga = c.kbins ? c.kbins + ((int64_t)d * c.R + l) * (na + nbb) : nullptr;
     kron_factor_sketch<T>(c.U[0] + (int64_t)l * c.I[0] * c.I[1], c.I[0], c.I[1], tab + c.off[0], tab + c.off[1],
-                          na, ya, lds);
+                          na, ya, lds, 1, ga);
     kron_factor_sketch<T, true>(c.U[1] + l, c.I[2], c.I[3], tab + c.off[2], tab + c.off[3], nbb, ya + na, lds,
-                                c.R);
+                                c.R, ga ? ga + na : nullptr);
 }
 
 // Second step, forward tile (sketch d, slice q, chunk of shared indices):
@@ -602,7 +616,7 @@ inline void desc_from_plan(CpDesc &c, const fcs_plan *p) {
 // LDS bytes a kernel of FFT size P needs for a computation.
 __host__ __device__ inline size_t cp_lds_bytes(int P, const CpDesc &c) {
     size_t b = (size_t)(P + P / 16) * 8;
-    if (c.kind == FCS_DESC_KRON || c.kind == FCS_DESC_CONTRACTION) {
+    if ((c.kind == FCS_DESC_KRON || c.kind == FCS_DESC_CONTRACTION) && !c.kbins) {
         const size_t na = (size_t)(c.J[0] + c.J[1] - 1), nb = (size_t)(c.J[2] + c.J[3] - 1);
         b = na * 8 > b ? na * 8 : b;
         b = nb * 8 > b ? nb * 8 : b;

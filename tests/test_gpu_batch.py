@@ -67,9 +67,28 @@ def test_kron_nonfinite_and_errors():
     p3 = Plan((4, 5, 6), (8, 8, 8), 1, 3, device=DEV)
     with pytest.raises(ValueError):
         p3.sketch_kron(colmajor(A), colmajor(A))
-    with pytest.raises(FcsError):   # 2 * 65536 bins do not fit in LDS
-        Plan((2, 2, 2, 2), (65536,) * 4, 1, 3, device=DEV).sketch_kron(dev(np.ones(4, np.float32)),
-                                                                       dev(np.ones(4, np.float32)))
+    with pytest.raises(FcsError):   # J~ = 1.2e6 exceeds every transform length (64 x 16384)
+        Plan((2, 2, 2, 2), (300000,) * 4, 1, 3, device=DEV).sketch_kron(dev(np.ones(4, np.float32)),
+                                                                        dev(np.ones(4, np.float32)))
+
+
+@pytest.mark.parametrize("J", [20000, 150000])
+def test_kron_long_hashes_sum_factor_bins_in_global_memory(J):
+    """The paper's Kronecker set-up (A 30 x 40, B 40 x 50, U[-5, 5]) at hash
+    lengths whose 64-bit factor-sketch bins exceed LDS (J~ = 4J - 3 up to
+    about 6e5, a compression ratio of 4): the bins are summed in global
+    memory, and the sketch still matches the oracle."""
+    I, D, seed = (30, 40, 40, 50), 2, 23
+    A = synth.uniform_matrix(21, (30, 40), stream=1)
+    B = synth.uniform_matrix(21, (40, 50), stream=2)
+    plan = Plan(I, (J,) * 4, D, seed, device=DEV)
+    y, _ = plan.sketch_kron(colmajor(A), colmajor(B))
+    y = y.cpu().numpy()
+    hs, ss = O.hash_tables(seed, D, I, (J,) * 4)
+    for d in range(D):
+        want = O.kron_fcs(A.astype(np.float32).astype(np.float64), B.astype(np.float32).astype(np.float64),
+                          hs[d], ss[d], (J,) * 4)
+        assert rel(y[d], want) <= TOL, (d, rel(y[d], want))
 
 
 def _instances(count, seed, kron_every=5, I_range=(8, 400), R_range=(1, 40), logJ_range=(5, 11)):

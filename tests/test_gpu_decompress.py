@@ -143,6 +143,21 @@ def test_contraction_matches_oracle(I, J, Lc, D, seed):
     assert np.linalg.norm(s1 - s2) <= 1e-5 * np.linalg.norm(s2)
 
 
+def test_contraction_with_long_hashes():
+    """Factor-sketch bins beyond LDS (J = 20000) are summed in global memory."""
+    I, J, Lc, D, seed = (30, 40, 40, 30), (20000,) * 4, 5, 2, 44
+    r = np.random.default_rng(24)
+    A = r.uniform(0, 10, (I[0], I[1], Lc)).astype(np.float32)
+    B = r.uniform(0, 10, (Lc, I[2], I[3])).astype(np.float32)
+    plan = Plan(I, J, D, seed, device=DEV)
+    y, _ = plan.sketch_contraction(_colmajor(A), _colmajor(B))
+    y = y.cpu().numpy().astype(np.float64)
+    hs, ss = O.hash_tables(seed, D, I, J)
+    for d in range(D):
+        want = O.contraction_fcs(A, B, hs[d], ss[d], J)
+        assert np.linalg.norm(y[d] - want) <= 1e-5 * np.linalg.norm(want), d
+
+
 def test_contraction_of_one_slice_is_the_kronecker_sketch():
     r = np.random.default_rng(30)
     A = r.uniform(-5, 5, (12, 10, 1)).astype(np.float32)
