@@ -92,21 +92,93 @@ def dense_workload(args, torch, dev):
     return cfg, res, cpu, T
 
 
+# ---------------------------------------------------------------------------
+# CPU baselines: the oracle as it stands, timed on the host cores with a
+# process pool over independent pieces of work (sketches d, instances).  The
+# pool is forked after the inputs exist, so the workers read them without a
+# copy; they run only oracle code (numpy and the plain C brute force).
+# ---------------------------------------------------------------------------
+_POOL = {}
+
+
+def host_cores():
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _pool_map(fn, items, cores):
+    """(results, wall seconds, processes used) of fn over items, forked."""
+    import multiprocessing as mp
+    procs = max(1, min(cores, len(items)))
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(procs) as pool:
+        res = pool.map(fn, items, chunksize=1)
+    return res, time.perf_counter() - t0, procs
+
+
+def _dense_one(d):
+    import oracle as O
+    st = _POOL
+    return O.dense_rows(st["T"], st["I"], [st["hs"][d]], [st["ss"][d]], st["Jt"], 0, st["rows"])
+
+
 def dense_cpu_baseline(cfg, T, Jt, sample_rows):
-    """The oracle (plain C FP64 brute force) on the first `sample_rows` rows
-    of the same tensor, scaled to sketches/s of the whole tensor."""
+    """The oracle (plain C FP64 brute force), one sketch per process, over
+    the first `sample_rows` rows of the same tensor, scaled to sketches/s of
+    the whole tensor."""
     import oracle as O
     rows = int(np.prod(cfg.I[1:]))
     sample_rows = min(rows, sample_rows)
     hs, ss = O.hash_tables(cfg.hash_seed, cfg.D, cfg.I, cfg.J)
-    O.dense_rows(T, cfg.I, hs, ss, Jt, 0, 64)    # load and warm the library
-    t0 = time.perf_counter()
-    O.dense_rows(T, cfg.I, hs, ss, Jt, 0, sample_rows)
-    dt = time.perf_counter() - t0
+    O.dense_rows(T, cfg.I, hs[:1], ss[:1], Jt, 0, 64)    # build and load the library
+    _POOL.update(T=T, I=cfg.I, hs=hs, ss=ss, Jt=Jt, rows=sample_rows)
+    _, dt, procs = _pool_map(_dense_one, list(range(cfg.D)), host_cores())
+    _POOL.clear()
     full = dt * rows / sample_rows
-    return {"value": cfg.D / full, "unit": "sketches/s", "cores": 1, "kind": "oracle",
-            "sample": f"rows 0..{sample_rows} of {rows} (mode-0 fibres of the 1024^3 tensor), "
-                      f"all {cfg.D} sketches, {dt:.2f} s, scaled to the full tensor"}
+    return {"value": cfg.D / full, "unit": "sketches/s", "cores": procs, "cpu": cpu_model(), "kind": "oracle",
+            "sample": f"rows 0..{sample_rows} of {rows} (mode-0 fibres of the 1024^3 tensor), all {cfg.D} "
+                      f"sketches, one per process, {dt:.2f} s wall, scaled to the full tensor"}
+
+
+def _coo_one(d):
+    import oracle as O
+    st = _POOL
+    return O.coo(st["idx"], st["val"], st["I"], [st["hs"][d]], [st["ss"][d]], st["Jt"])
+
+
+def _cp_one(job):
+    import oracle as O
+    st = _POOL
+    d, r0, r1 = job
+    U = [u[:, r0:r1] for u in st["U"]]
+    return O.fcs_cp_fft(None, U, st["hs"][d], st["ss"][d], st["J"], st["L"])
+
+
+def _batch_one(k):
+    import oracle as O
+    import synth
+    st = _POOL
+    ins = st["insts"][k]
+    F = ins.factors()
+    hs, ss = O.hash_tables(ins.hash_seed, 1, ins.I, ins.J)
+    if ins.kind == "kron":
+        return O.kron_fcs(F[0].astype(np.float64), F[1].astype(np.float64), hs[0], ss[0], ins.J)
+    return O.fcs_cp_fft(None, F, hs[0], ss[0], ins.J, int(2 ** np.ceil(np.log2(O.sketch_length(ins.J)))))
 
 
 def cp_workload(args, torch, dev, cfg, pairs=0, inner=False):
@@ -133,10 +205,39 @@ def cp_workload(args, torch, dev, cfg, pairs=0, inner=False):
     # forward transforms: D sketches x stored slices x R ranks x N modes,
     # 5 P log2 P flops each (the usual complex radix-2 count)
     fft_flop = cfg.D * (plan.Q // 2 + 1) * R * len(cfg.I) * 5.0 * plan.P * lg
+    # algorithmic work: D N R real-to-complex transforms of the power of two
+    # L >= J~, 2.5 L log2 L flops each (half a complex transform)
+    Lp2 = 1 << int(np.ceil(np.log2(plan.Jt)))
+    alg_flop = cfg.D * len(cfg.I) * R * 2.5 * Lp2 * np.log2(Lp2)
     res = {"workload": cfg.name, "I": list(cfg.I), "J": list(cfg.J), "R": R, "D": cfg.D, "L": plan.L,
            "P": plan.P, "Q": plan.Q, "ms": ms, "sketches_per_s": cfg.D / (ms * 1e-3),
            "fft_gflop": fft_flop / 1e9, "fft_tflops": fft_flop / (ms * 1e-3) / 1e12,
-           "frac_fp32_peak": fft_flop / (ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS}
+           "alg_L": Lp2, "alg_gflop": alg_flop / 1e9, "alg_tflops": alg_flop / (ms * 1e-3) / 1e12,
+           "frac_fp32_peak": alg_flop / (ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS}
+    if Lp2 != plan.L and plan.Jt <= 65536:
+        # the same sketch at the power-of-two length L = 2^k >= J~
+        p2 = Plan(cfg.I, cfg.J, cfg.D, cfg.hash_seed, L=Lp2, device=dev)
+        ws2 = p2.workspace(2, R=R)
+        out2 = torch.empty_like(out)
+        p2.sketch_cp(Ud, out=out2, ws=ws2, stream=stream)
+        ms2, _ = event_timer(torch, stream, lambda: p2.sketch_cp(Ud, out=out2, ws=ws2, stream=stream),
+                             max(3, args.steps // 2))
+        res["at_alg_L"] = {"L": Lp2, "P": p2.P, "Q": p2.Q, "ms": ms2, "sketches_per_s": cfg.D / (ms2 * 1e-3),
+                           "frac_fp32_peak": alg_flop / (ms2 * 1e-3) / 1e12 / FP32_PEAK_TFLOPS,
+                           "rel_diff_vs_default_L": float(torch.linalg.norm((out2 - out).double())
+                                                          / torch.linalg.norm(out.double()))}
+        p2.close()
+    if not args.no_cpu_baseline and cfg.R >= 64:
+        import oracle as O
+        hs, ss = O.hash_tables(cfg.hash_seed, cfg.D, cfg.I, cfg.J)
+        rs = 8                                  # ranks per sample job
+        _POOL.update(U=U, hs=hs, ss=ss, J=cfg.J, L=Lp2)
+        _, dt, procs = _pool_map(_cp_one, [(d, 0, rs) for d in range(cfg.D)], host_cores())
+        _POOL.clear()
+        full = dt * R / rs
+        res["cpu_baseline"] = {"value": cfg.D / full, "unit": "sketches/s", "cores": procs, "cpu": cpu_model(),
+                               "kind": "oracle", "sample": f"ranks 0..{rs} of {R} (FP64 FFT route, L = {Lp2}), all "
+                               f"{cfg.D} sketches, one per process, {dt:.2f} s wall, scaled to all ranks"}
     if inner:
         # the order-3 I_n = 100 outputs: the sketch of a second random rank-R
         # CP tensor, the median over D of the sketch inner products
@@ -202,7 +303,6 @@ def coo_workload(args, torch, dev, T):
     nnz = val.size
     idx_d = torch.from_numpy(idx).to(dev)
     val_d = torch.from_numpy(val).to(dev)
-    del idx, val
     plan = Plan(cfg.I, cfg.J, cfg.D, cfg.hash_seed, device=dev)
     out = torch.empty((cfg.D, plan.Jt), dtype=torch.float32, device=dev)
     ws = plan.workspace(1)
@@ -215,8 +315,22 @@ def coo_workload(args, torch, dev, T):
         step()
     ms, _ = event_timer(torch, stream, step, max(3, args.steps // 2))
     alg = 16 * nnz
-    return {"workload": "dense1024 10% COO", "nnz": nnz, "ms": ms, "sketches_per_s": cfg.D / (ms * 1e-3),
-            "alg_bytes": alg, "achieved_gbs": alg / (ms * 1e-3) / 1e9}
+    res = {"workload": "dense1024 10% COO", "nnz": nnz, "ms": ms, "sketches_per_s": cfg.D / (ms * 1e-3),
+           "alg_bytes": alg, "achieved_gbs": alg / (ms * 1e-3) / 1e9}
+    if not args.no_cpu_baseline:
+        import oracle as O
+        sample = min(nnz, 1 << 24)
+        hs, ss = O.hash_tables(cfg.hash_seed, cfg.D, cfg.I, cfg.J)
+        _POOL.update(idx=np.ascontiguousarray(idx[:, :sample]), val=np.ascontiguousarray(val[:sample]),
+                     I=cfg.I, hs=hs, ss=ss, Jt=plan.Jt)
+        _, dt, procs = _pool_map(_coo_one, list(range(cfg.D)), host_cores())
+        _POOL.clear()
+        full = dt * nnz / sample
+        res["cpu_baseline"] = {"value": cfg.D / full, "unit": "sketches/s", "cores": procs, "cpu": cpu_model(),
+                               "kind": "oracle", "sample": f"first {sample} of {nnz} entries, all {cfg.D} "
+                               f"sketches, one per process, {dt:.2f} s wall, scaled to all entries"}
+    del idx, val
+    return res
 
 
 def batch_inputs(torch, dev, count):
@@ -256,6 +370,20 @@ def batch_flops(items):
         else:
             R = int(it["U"][0].shape[0])
             total += p.D * Qh * (p.N * R + 1) * per
+    return total
+
+
+def batch_alg_flops(insts):
+    """Algorithmic transform work of the batch: per CP instance D N R
+    real-to-complex transforms of the power of two L >= J~ (2.5 L log2 L
+    flops each); per Kronecker instance D x 2 such transforms (one per factor
+    sketch)."""
+    import oracle as O
+    total = 0.0
+    for ins in insts:
+        L = 1 << int(np.ceil(np.log2(O.sketch_length(ins.J))))
+        per = 2.5 * L * np.log2(L)
+        total += ins.D * (2 if ins.kind == "kron" else len(ins.I) * ins.R) * per
     return total
 
 
@@ -373,6 +501,7 @@ def batch_workload(args, torch, dev):
     nsk = sum(it["plan"].D for it in items)
     flops = batch_flops(items)
     plain_flops = batch_flops(plain_items)
+    alg = batch_alg_flops(insts)
     base_ms = plain_graph_ms if plain_graph_ms is not None else plain_eager_ms
     if plain_tuned_ms is not None:
         base_ms = min(base_ms, plain_tuned_ms)
@@ -388,10 +517,21 @@ def batch_workload(args, torch, dev):
            "speedup_vs_plain_eager": plain_eager_ms / batch_ms,
            "fft_tflops_batched": flops / (batch_ms * 1e-3) / 1e12,
            "fft_tflop_batched": flops / 1e12, "fft_tflop_plain": plain_flops / 1e12,
-           "frac_fp32_peak": flops / (batch_ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS,
+           "alg_tflop": alg / 1e12, "alg_tflops_batched": alg / (batch_ms * 1e-3) / 1e12,
+           "frac_fp32_peak": alg / (batch_ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS,
            "max_rel_err_vs_plain": worst, "tuned_config": cfg, "tuned_gather_weight": weight,
            "length_trials": len_table, "tune_s": tune_s, "tune_trials": len(trials), "setup_s": setup_s}
     b.close()
+    if not args.no_cpu_baseline:
+        step = max(1, n // 128)
+        sample = list(range(0, n, step))
+        _POOL.update(insts=insts)
+        _, dt, procs = _pool_map(_batch_one, sample, host_cores())
+        _POOL.clear()
+        full = dt * n / len(sample)
+        res["cpu_baseline"] = {"value": nsk / full, "unit": "sketches/s", "cores": procs, "cpu": cpu_model(),
+                               "kind": "oracle", "sample": f"every {step}th instance ({len(sample)} of {n}, FP64 "
+                               f"FFT route at L = 2^k >= J~), one per process, {dt:.2f} s wall, scaled to all"}
     return res
 
 
@@ -702,16 +842,46 @@ def serve_workload(args, torch, dev):
     # one request at a time on the same stream, each waited for
     reqs = serve_requests(srv, args, rates[-1], int(min(args.serve_max, 4000)), 100 + len(rates) - 1)
     torch.cuda.synchronize()
+    service = {}
     t1 = time.perf_counter()
     for r in reqs:
+        ta = time.perf_counter()
         run_alone(srv, r)
+        service.setdefault(r.kind, []).append(time.perf_counter() - ta)
         r.result = None
     plain_s = time.perf_counter() - t1
     sk = sum(r.sketches for r in reqs)
     out["plain"] = {"requests": len(reqs), "wall_s": plain_s, "req_s": len(reqs) / plain_s,
-                    "sketches_per_s": sk / plain_s}
+                    "sketches_per_s": sk / plain_s,
+                    "mean_service_ms": {k: 1e3 * float(np.mean(v)) for k, v in service.items()}}
     best = max(out["rates"], key=lambda x: x["served_req_s"])
     out["served_vs_plain_req_s"] = best["served_req_s"] / out["plain"]["req_s"]
+    # the plain path at each offered rate: the same arrivals through one
+    # first-come first-served server whose service times are the measured
+    # one-at-a-time times of requests of the same kind
+    for k, row in enumerate(out["rates"]):
+        reqs = serve_requests(srv, args, row["offered_req_s"], row["requests"], 100 + k)
+        pos = {kind: 0 for kind in service}
+        free = 0.0
+        lat = []
+        for r in sorted(reqs, key=lambda q: q.arrival):
+            v = service[r.kind]
+            sv = v[pos[r.kind] % len(v)]
+            pos[r.kind] += 1
+            start = max(r.arrival, free)
+            free = start + sv
+            lat.append(free - r.arrival)
+        makespan = free - min(r.arrival for r in reqs)
+        plain_rate = len(reqs) / makespan
+        row["plain_req_s"] = plain_rate
+        row["plain_p50_ms"] = float(np.percentile(lat, 50) * 1e3)
+        row["plain_p99_ms"] = float(np.percentile(lat, 99) * 1e3)
+        row["served_vs_plain_req_s"] = row["served_req_s"] / plain_rate
+        arr = sorted(r.arrival for r in reqs)
+        row["arrival_req_s"] = (len(arr) - 1) / max(arr[-1] - arr[0], 1e-9)
+        # saturated: completions fall clearly behind the arrivals
+        row["saturated"] = bool(row["served_req_s"] < 0.9 * row["arrival_req_s"])
+        row["plain_saturated"] = bool(plain_rate < 0.9 * row["arrival_req_s"])
     # alone-versus-mix parity on a sample of a mixed run
     reqs = serve_requests(srv, args, rates[len(rates) // 2], 600, 4242)
     srv.run(reqs, timeout=120)
@@ -882,7 +1052,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=1 << 19,
+    ap.add_argument("--cpu-rows", type=int, default=1 << 20,
                     help="rows of the tensor the CPU oracle sketches")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "dense1024_traffic.json"))
     ap.add_argument("--mode", default="full", choices=["full", "dense", "coo", "cp", "batch", "serve", "rtpm", "als", "decompress", "compare",
