@@ -580,22 +580,29 @@ def serve_requests(srv, args, rate, count, seed):
     return reqs
 
 
+def noise_std(sigma, R, I):
+    """Per-entry standard deviation of the Gaussian noise at level sigma for
+    the decomposition experiments: sigma is read as the noise-to-signal
+    energy ratio, ||N||^2 = sigma ||T_clean||^2, with ||T_clean|| = sqrt(R)
+    for unit weights and orthonormal factors (plain ALS then leaves exactly
+    the residual sqrt(sigma), the value the paper prints for it)."""
+    return np.sqrt(sigma) * np.sqrt(R) / I ** 1.5
+
+
 def rtpm_workload(args, torch, dev):
     """Sketched robust tensor power method (Section 4.1.1, RTPM) in the setting of
     the paper's synthetic experiment: a symmetric 100^3 tensor of CP rank 10
-    (orthonormal basis, unit weights) plus Gaussian noise at level 0.01 (read
-    as ||N|| = 0.01 ||T||), D = 2 sketches, 15 starts, 20 power iterations,
-    J_n = 5000.  Timed: the dense
-    sketch of the tensor plus the whole decomposition (host syncs for the
-    choice of start included).  Quality: residual ||T - sum lam u o u o u|| /
-    ||T|| and the overlap of each component with the planted basis."""
+    (orthonormal basis, unit weights) plus Gaussian noise at level 0.01 (an
+    energy ratio, ||N|| = 0.1 ||T||), D = 2 sketches, 15 starts, 20 power
+    iterations, J_n = 5000.  Timed: the dense sketch of the tensor plus the
+    whole decomposition.  Quality: residual ||T - sum lam u o u o u|| / ||T||
+    against the noisy and against the clean tensor, and the overlap of each
+    component with the planted basis."""
     import synth
     from paper_2106_13062_amd import Plan
     from paper_2106_13062_amd.rtpm import rtpm
     I, R, D, L, iters, J, sigma = 100, 10, 2, 15, 20, 5000, 0.01
-    # noise level sigma read relative to the tensor: ||N|| = sigma ||T_clean||
-    # (per-entry std sigma * ||T_clean|| / sqrt(I^3); ||T_clean|| = sqrt(R))
-    Tv, A = synth.symmetric_cp_tensor(synth.DATA_SEED["rtpm100"], I, np.ones(R), sigma * np.sqrt(R) / I ** 1.5)
+    Tv, A = synth.symmetric_cp_tensor(synth.DATA_SEED["rtpm100"], I, np.ones(R), noise_std(sigma, R, I))
     starts = torch.from_numpy(synth.rtpm_starts(synth.DATA_SEED["rtpm100"], R, L, I, stream=7)).to(dev)
     plan = Plan((I, I, I), (J, J, J), D, synth.HASH_SEED["rtpm100"], device=dev)
     T = torch.from_numpy(Tv.astype(np.float32)).to(dev)
@@ -619,9 +626,9 @@ def rtpm_workload(args, torch, dev):
     clean = torch.from_numpy(synth.symmetric_cp_tensor(synth.DATA_SEED["rtpm100"], I, np.ones(R))[0]).to(dev)
     resid_clean = (torch.linalg.vector_norm(clean - approx) / torch.linalg.vector_norm(clean)).item()
     overlap = np.abs(U.double().cpu().numpy() @ A).max(axis=1)
-    return {"workload": "rtpm100: symmetric 100^3 CP rank 10 (orthonormal basis, unit weights) + Gaussian noise of "
-                        "norm 0.01 ||T||, D=2, 15 starts, 20 iterations, J_n=5000", "ms": ms, "residual": resid,
-            "noise_floor": sigma * np.sqrt(R) / float(Td.norm()),
+    return {"workload": "rtpm100: symmetric 100^3 CP rank 10 (orthonormal basis, unit weights) + Gaussian noise "
+                        "at energy ratio 0.01 (||N|| = 0.1 ||T||), D=2, 15 starts, 20 iterations, J_n=5000", "ms": ms,
+            "residual": resid, "noise_floor": float(np.sqrt(sigma)),
             "residual_vs_clean": resid_clean, "min_overlap": float(overlap.min()),
             "eigenvalues": [round(float(x), 5) for x in lam]}
 
@@ -629,8 +636,8 @@ def rtpm_workload(args, torch, dev):
 def rtpm_asym_workload(args, torch, dev):
     """RTPM by alternating rank-1 updates (the asymmetric form of Section 4.1.1)
     on an asymmetric 100^3 tensor of CP rank 10 (three independent
-    orthonormal factors, unit weights) plus Gaussian noise at level 0.01
-    (relative), D = 10 (the paper's asymmetric experiments use 10 and 15),
+    orthonormal factors, unit weights) plus Gaussian noise at energy ratio
+    0.01, D = 10 (the paper's asymmetric experiments use 10 and 15),
     15 starts, 20 iterations, J_n = 5000.  Timed: the dense sketch plus the
     whole decomposition.  Quality: residual and the smallest overlap of a
     recovered vector with its planted factor."""
@@ -638,8 +645,7 @@ def rtpm_asym_workload(args, torch, dev):
     from paper_2106_13062_amd import Plan
     from paper_2106_13062_amd.rtpm import rtpm_asym
     I, R, D, L, iters, J, sigma = 100, 10, 10, 15, 20, 5000, 0.01
-    Tv, F = synth.asymmetric_cp_tensor(synth.DATA_SEED["rtpm_asym100"], I, np.ones(R),
-                                       sigma * np.sqrt(R) / I ** 1.5)
+    Tv, F = synth.asymmetric_cp_tensor(synth.DATA_SEED["rtpm_asym100"], I, np.ones(R), noise_std(sigma, R, I))
     starts = torch.from_numpy(synth.rtpm_asym_starts(synth.DATA_SEED["rtpm_asym100"], R, L, I, stream=7)).to(dev)
     plan = Plan((I, I, I), (J, J, J), D, synth.HASH_SEED["rtpm_asym100"], device=dev)
     T = torch.from_numpy(Tv.astype(np.float32)).to(dev)
@@ -662,92 +668,117 @@ def rtpm_asym_workload(args, torch, dev):
     resid = (torch.linalg.vector_norm(Td - approx) / torch.linalg.vector_norm(Td)).item()
     overlap = min(float(np.abs(Xd[n].cpu().numpy() @ F[n]).max(axis=1).min()) for n in range(3))
     plan.close()
-    return {"workload": "rtpm_asym100: asymmetric 100^3 CP rank 10 (orthonormal factors, unit weights) + noise of "
-                        "norm 0.01 ||T||, D=10, 15 starts, 20 iterations, J_n=5000", "ms": ms, "residual": resid,
+    return {"workload": "rtpm_asym100: asymmetric 100^3 CP rank 10 (orthonormal factors, unit weights) + noise at "
+                        "energy ratio 0.01, D=10, 15 starts, 20 iterations, J_n=5000", "ms": ms, "residual": resid,
             "min_overlap": overlap, "eigenvalues": [round(float(x), 5) for x in lam]}
 
 
 def rtpm50_workload(args, torch, dev):
     """Sketched RTPM in the setting of the paper's HCS-versus-FCS table: a
     symmetric 50^3 tensor of CP rank 10 (orthonormal basis, unit weights)
-    plus Gaussian noise at level 0.01 (relative, as for the 100^3 case),
-    J_n in {200, 300, 400} and D in {10, 20}, 15 starts and 20 iterations
-    per component.  Each cell is timed (sketch plus decomposition) and
-    reports the relative residual ||T - sum lam u o u o u|| / ||T||."""
+    plus Gaussian noise at energy ratio sigma in {0.01, 0.1}, J_n in
+    {200, 300, 400} and D in {10, 20}, 15 starts and 20 iterations per
+    component.  Each cell is timed (sketch plus decomposition) and reports
+    the relative residual against the noisy tensor and against the clean
+    one (the paper's values fall below the noise level at sigma = 0.1, so
+    they measure the recovery of the clean tensor)."""
     import synth
     from paper_2106_13062_amd import Plan
     from paper_2106_13062_amd.rtpm import rtpm
-    I, R, L, iters, sigma = 50, 10, 15, 20, 0.01
-    Tv, A = synth.symmetric_cp_tensor(synth.DATA_SEED["rtpm50"], I, np.ones(R), sigma * np.sqrt(R) / I ** 1.5)
+    I, R, L, iters = 50, 10, 15, 20
     starts = torch.from_numpy(synth.rtpm_starts(synth.DATA_SEED["rtpm50"], R, L, I, stream=7)).to(dev)
-    T = torch.from_numpy(Tv.astype(np.float32)).to(dev)
-    Td = T.double()
+    clean = torch.from_numpy(synth.symmetric_cp_tensor(synth.DATA_SEED["rtpm50"], I, np.ones(R))[0]).to(dev)
     cells = []
-    for D in (10, 20):
-        for J in (200, 300, 400):
-            plan = Plan((I, I, I), (J, J, J), D, synth.HASH_SEED["rtpm50"], device=dev)
+    for sigma in (0.01, 0.1):
+        Tv, A = synth.symmetric_cp_tensor(synth.DATA_SEED["rtpm50"], I, np.ones(R), noise_std(sigma, R, I))
+        T = torch.from_numpy(Tv.astype(np.float32)).to(dev)
+        Td = T.double()
+        for D in (10, 20):
+            for J in (200, 300, 400):
+                plan = Plan((I, I, I), (J, J, J), D, synth.HASH_SEED["rtpm50"], device=dev)
 
-            def run():
-                y = plan.sketch_dense(T)
-                return rtpm(plan, y, starts, iters)
+                def run():
+                    y = plan.sketch_dense(T)
+                    return rtpm(plan, y, starts, iters)
 
-            run()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            lam, U = run()
-            torch.cuda.synchronize()
-            ms = (time.perf_counter() - t0) * 1e3
-            Ud = U.double()
-            approx = torch.einsum("r,ir,jr,kr->kji", lam.to(dev), Ud.T, Ud.T, Ud.T).reshape(-1)
-            resid = (torch.linalg.vector_norm(Td - approx) / torch.linalg.vector_norm(Td)).item()
-            cells.append({"D": D, "J": J, "ms": ms, "residual": resid})
-            plan.close()
-    return {"workload": "rtpm50: symmetric 50^3 CP rank 10 + noise of norm 0.01 ||T||, 15 starts, 20 iterations",
-            "cells": cells}
+                run()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                lam, U = run()
+                torch.cuda.synchronize()
+                ms = (time.perf_counter() - t0) * 1e3
+                Ud = U.double()
+                approx = torch.einsum("r,ir,jr,kr->kji", lam.to(dev), Ud.T, Ud.T, Ud.T).reshape(-1)
+                resid = (torch.linalg.vector_norm(Td - approx) / torch.linalg.vector_norm(Td)).item()
+                resid_clean = (torch.linalg.vector_norm(clean - approx) / torch.linalg.vector_norm(clean)).item()
+                cells.append({"sigma": sigma, "D": D, "J": J, "ms": ms, "residual": resid,
+                              "residual_vs_clean": resid_clean})
+                plan.close()
+    return {"workload": "rtpm50: symmetric 50^3 CP rank 10 + noise at energy ratio 0.01 and 0.1, 15 starts, "
+                        "20 iterations", "cells": cells}
 
 
 def als_workload(args, torch, dev):
     """Sketched alternating least squares (Section 4.1.2, ALS) in the setting of
     the paper's synthetic experiment: an asymmetric 400^3 tensor of CP rank
     10 (three independent orthonormal factors, unit weights) plus Gaussian
-    noise at level 0.01 (read as ||N|| = 0.01 ||T||), D = 10 sketches,
-    J_n = 5000, 20 iterations from N(0, 1) starting factors.  Timed: the dense
-    sketch of the tensor plus the whole decomposition.  Quality: residual
-    ||T - sum lam a o b o c|| / ||T|| and the overlap of each recovered
-    column with the planted factors."""
+    noise at energy ratio sigma in {0.01, 0.1} (plain ALS would leave
+    residual sqrt(sigma): 0.1 and 0.316), D = 10 sketches, J_n = 5000, 20
+    iterations.  Two starts: N(0, 1) factors, and the factors found by the
+    sketched asymmetric power method (15 starts, 20 iterations) on the same
+    sketch.  Timed: the dense sketch plus the whole decomposition (and the
+    power method for the second start).  Quality: residual
+    ||T - sum lam a o b o c|| / ||T|| against the noisy and the clean tensor,
+    and the overlap of each recovered column with the planted factors."""
     import synth
     from paper_2106_13062_amd import Plan
     from paper_2106_13062_amd.als import als
-    I, R, D, iters, J, sigma = 400, 10, 10, 20, 5000, 0.01
-    Tv, F = synth.asymmetric_cp_tensor(synth.DATA_SEED["als400"], I, np.ones(R), sigma * np.sqrt(R) / I ** 1.5)
-    T = torch.from_numpy(Tv.astype(np.float32)).to(dev)
-    del Tv
-    init = [torch.from_numpy(f).to(dev) for f in synth.als_init(synth.DATA_SEED["als400"], I, R, stream=9)]
+    from paper_2106_13062_amd.rtpm import rtpm_asym
+    I, R, D, iters, J = 400, 10, 10, 20, 5000
     plan = Plan((I, I, I), (J, J, J), D, synth.HASH_SEED["als400"], device=dev)
+    rand_init = [torch.from_numpy(f).to(dev) for f in synth.als_init(synth.DATA_SEED["als400"], I, R, stream=9)]
+    starts = torch.from_numpy(synth.rtpm_asym_starts(synth.DATA_SEED["als400"], R, 15, I, stream=11)).to(dev)
+    cleanv, F = synth.asymmetric_cp_tensor(synth.DATA_SEED["als400"], I, np.ones(R))
+    clean = torch.from_numpy(cleanv).to(dev)
+    del cleanv
+    runs = []
+    for sigma in (0.01, 0.1):
+        Tv, _ = synth.asymmetric_cp_tensor(synth.DATA_SEED["als400"], I, np.ones(R), noise_std(sigma, R, I))
+        T = torch.from_numpy(Tv.astype(np.float32)).to(dev)
+        del Tv
+        Td = T.double()
+        for start in ("random", "rtpm"):
 
-    def run():
-        y = plan.sketch_dense(T)
-        return als(plan, y, init, iters)
+            def run():
+                y = plan.sketch_dense(T)
+                if start == "random":
+                    init = rand_init
+                else:
+                    _, X = rtpm_asym(plan, y, starts, 20)
+                    init = [x.t().contiguous() for x in X]
+                return als(plan, y, init, iters)
 
-    run()
-    torch.cuda.synchronize()
-    reps = 3
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        lam, G = run()
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / reps
-    Gd = [g.double() for g in G]
-    approx = torch.einsum("r,ir,jr,kr->kji", lam, *Gd).reshape(-1)
-    Td = T.double()
-    resid = (torch.linalg.vector_norm(Td - approx) / torch.linalg.vector_norm(Td)).item()
-    del approx, Td
-    overlap = min(float(np.abs(Gd[n].cpu().numpy().T @ F[n]).max(axis=1).min()) for n in range(3))
+            run()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            lam, G = run()
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3
+            Gd = [g.double() for g in G]
+            approx = torch.einsum("r,ir,jr,kr->kji", lam, *Gd).reshape(-1)
+            resid = (torch.linalg.vector_norm(Td - approx) / torch.linalg.vector_norm(Td)).item()
+            resid_clean = (torch.linalg.vector_norm(clean - approx) / torch.linalg.vector_norm(clean)).item()
+            del approx
+            overlap = min(float(np.abs(Gd[n].cpu().numpy().T @ F[n]).max(axis=1).min()) for n in range(3))
+            runs.append({"sigma": sigma, "start": start, "ms": ms, "residual": resid,
+                         "residual_vs_clean": resid_clean, "plain_als_residual": float(np.sqrt(sigma)),
+                         "min_overlap": overlap, "weights": [round(float(x), 5) for x in lam.cpu()]})
+        del T, Td
+        torch.cuda.empty_cache()
     plan.close()
     return {"workload": "als400: asymmetric 400^3 CP rank 10 (orthonormal factors, unit weights) + Gaussian noise "
-                        "of norm 0.01 ||T||, D=10, J_n=5000, 20 iterations", "ms": ms, "residual": resid,
-            "noise_floor": sigma, "min_overlap": overlap,
-            "weights": [round(float(x), 5) for x in lam.cpu()]}
+                        "at energy ratio 0.01 and 0.1, D=10, J_n=5000, 20 iterations from random or power-method "
+                        "starts", "runs": runs}
 
 
 def decompress_workload(args, torch, dev):

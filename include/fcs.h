@@ -461,6 +461,46 @@ FCS_API fcs_status fcs_batch_run(fcs_batch_t batch, void *ws, size_t ws_bytes,
 
 FCS_API fcs_status fcs_batch_destroy(fcs_batch_t batch);
 
+/* ---------------------------------------------------------------------------
+ * Small dense steps of the decomposition drivers (the robust tensor power
+ * method of Section 4.1.1 and alternating least squares of Section 4.1.2),
+ * on sketch-sized data, asynchronous on `stream`; norms in double.
+ * ------------------------------------------------------------------------- */
+
+/* out[r][:] = in[r][:] / ||in[r][:]||_2 for P rows of n entries (row-major);
+ * exactly one of in64 (double) and in32 (float) is given; out is float;
+ * norms (device, double, P values) may be NULL.  A zero row stays zero.
+ * Errors: FCS_EINVAL, FCS_EDEVICE. */
+FCS_API fcs_status fcs_normalize_rows(int64_t P, int64_t n, const double *in64, const float *in32,
+                              float *out, double *norms, void *stream);
+
+/* The power method's choice among starts: j = the first index of the
+ * largest of vals[0..P) (NaN never wins), then row_out[0..n) = rows[j][:]
+ * (rows: P x n float, row-major) and, where given, *val_out = (float)
+ * vals[j], *val64_out = vals[j], *index_out = j (all device pointers).
+ * Errors: FCS_EINVAL, FCS_EDEVICE. */
+FCS_API fcs_status fcs_select_max(int64_t P, const double *vals, int64_t n, const float *rows,
+                          float *row_out, float *val_out, double *val64_out,
+                          int32_t *index_out, void *stream);
+
+/* y += a x for n floats (deflation of a sketch or spectrum by a rank-1
+ * term).  Errors: FCS_EINVAL, FCS_EDEVICE. */
+FCS_API fcs_status fcs_axpy(int64_t n, float a, const float *x, float *y, void *stream);
+
+/* One ALS factor update: with G the Hadamard product over the other modes
+ * of F_m F_m^T (R x R, double; F_m = others[m], R x Iother[m] float
+ * row-major, i.e. the factor's columns as rows), solve G X = Mt (Mt: R x In
+ * double, the mode's unfolding times the Khatri-Rao product of the other
+ * factors, transposed) by Cholesky, then lam[r] = ||X[r][:]||_2 and
+ * Ft_out[r][:] = X[r][:] / lam[r] (float, R x In).  ws: device workspace of
+ * fcs_als_workspace_bytes(R, In) bytes.  G must be positive definite (a
+ * non-positive pivot gives NaN outputs).  Errors: FCS_EINVAL, FCS_ENOMEM,
+ * FCS_EUNSUPPORTED (R > 90), FCS_EDEVICE. */
+FCS_API size_t fcs_als_workspace_bytes(int32_t R, int64_t In);
+FCS_API fcs_status fcs_als_update(int32_t R, int64_t In, const double *Mt, int32_t nother,
+                          const float *const *others, const int64_t *Iother, float *Ft_out,
+                          double *lam, void *ws, size_t ws_bytes, void *stream);
+
 /* Text of a status code (static storage). */
 FCS_API const char *fcs_status_str(fcs_status status);
 

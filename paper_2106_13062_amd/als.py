@@ -9,15 +9,15 @@ other factors at their own modes and the identity at mode n, and all R
 columns come from one batched free-mode contraction of the sketch spectra
 (fcs_contract_free_mode with P = R vector pairs, median over the D
 sketches).  The least-squares solve against the Hadamard product of the
-other factors' R x R Gram matrices and the normalisation of the columns into
-the weights are small dense steps done with torch on the device; every
-sketch and contraction runs in the library's kernels.
+other factors' R x R Gram matrices (Cholesky, in double) and the
+normalisation of the columns into the weights run in one library call
+(fcs_als_update); torch only holds the device memory.
 """
 from __future__ import annotations
 
 import torch
 
-from .fcs import Plan
+from .fcs import Plan, als_update
 
 
 def als(plan: Plan, y: torch.Tensor, init, iters: int, stream=None):
@@ -47,11 +47,5 @@ def als(plan: Plan, y: torch.Tensor, init, iters: int, stream=None):
                 for m in o:
                     vecs[m] = Ft[m]
                 Mt = plan.contract_free_mode(spec, n, vecs, stream=s)       # R x I_n, float64
-                G = torch.ones((R, R), dtype=torch.float64, device=y.device)
-                for m in o:
-                    f = Ft[m].to(torch.float64)
-                    G = G * (f @ f.t())
-                Ut = torch.linalg.solve(G, Mt)
-                lam = torch.linalg.vector_norm(Ut, dim=1)
-                Ft[n] = (Ut / lam[:, None]).to(torch.float32).contiguous()
+                Ft[n], lam = als_update(Mt, [Ft[m] for m in o], stream=s)
     return lam, [f.t().contiguous() for f in Ft]

@@ -425,3 +425,79 @@ def inner_median(a: torch.Tensor, b: torch.Tensor, stream=None):
     per_d = torch.empty(D, dtype=torch.float64, device=a.device)
     C.check(lib.fcs_inner_median(D, n, _ptr(a), _ptr(b), _ptr(med), _ptr(per_d), None, 0, _stream(stream)))
     return med, per_d
+
+
+# ---------------------------------------------------------------------------
+# small dense steps of the decomposition drivers (argument marshalling only)
+# ---------------------------------------------------------------------------
+def normalize_rows(x: torch.Tensor, out=None, norms=None, stream=None) -> torch.Tensor:
+    """fcs_normalize_rows: unit rows of a P x n float64 or float32 tensor,
+    returned as float32."""
+    lib = C.load()
+    if x.dtype not in (torch.float64, torch.float32):
+        raise TypeError("x must be float64 or float32")
+    _need(x, x.dtype, "x")
+    if x.dim() != 2:
+        raise ValueError("x must be P x n")
+    out = torch.empty(x.shape, dtype=torch.float32, device=x.device) if out is None else out
+    _need(out, torch.float32, "out")
+    in64 = x if x.dtype == torch.float64 else None
+    in32 = x if x.dtype == torch.float32 else None
+    C.check(lib.fcs_normalize_rows(int(x.shape[0]), int(x.shape[1]), _ptr(in64), _ptr(in32), _ptr(out),
+                                   _ptr(norms), _stream(stream)))
+    return out
+
+
+def select_max(vals: torch.Tensor, rows: torch.Tensor, row_out=None, val_out=None, val64_out=None,
+               stream=None):
+    """fcs_select_max: the row of the largest value (first on ties) into
+    row_out (1 x n float32), its value as float32 and float64 device
+    scalars."""
+    lib = C.load()
+    _need(vals, torch.float64, "vals")
+    _need(rows, torch.float32, "rows")
+    P, n = int(rows.shape[0]), int(rows.shape[1])
+    if vals.numel() != P:
+        raise ValueError("one value per row")
+    dev = rows.device
+    row_out = torch.empty((1, n), dtype=torch.float32, device=dev) if row_out is None else row_out
+    val_out = torch.empty(1, dtype=torch.float32, device=dev) if val_out is None else val_out
+    val64_out = torch.empty(1, dtype=torch.float64, device=dev) if val64_out is None else val64_out
+    C.check(lib.fcs_select_max(P, _ptr(vals), n, _ptr(rows), _ptr(row_out), _ptr(val_out), _ptr(val64_out),
+                               None, _stream(stream)))
+    return row_out, val_out, val64_out
+
+
+def axpy(a: float, x: torch.Tensor, y: torch.Tensor, stream=None) -> torch.Tensor:
+    """fcs_axpy: y += a x (float32, same number of entries), in place."""
+    lib = C.load()
+    _need(x, torch.float32, "x")
+    _need(y, torch.float32, "y")
+    if x.numel() != y.numel():
+        raise ValueError("x and y must have the same number of entries")
+    C.check(lib.fcs_axpy(y.numel(), float(a), _ptr(x), _ptr(y), _stream(stream)))
+    return y
+
+
+def als_update(Mt: torch.Tensor, others, out=None, lam=None, ws=None, stream=None):
+    """fcs_als_update: solve (Hadamard product of F_m F_m^T) X = Mt by
+    Cholesky and normalise the rows of X.  Mt: R x In float64; others: list
+    of R x I_m float32 (factors with their columns as rows).  Returns
+    (float32 R x In unit rows, float64 R weights)."""
+    lib = C.load()
+    _need(Mt, torch.float64, "Mt")
+    R, In = int(Mt.shape[0]), int(Mt.shape[1])
+    for m, f in enumerate(others):
+        _need(f, torch.float32, f"others[{m}]")
+        if f.dim() != 2 or int(f.shape[0]) != R:
+            raise ValueError("every other factor must be R x I_m")
+    dev = Mt.device
+    out = torch.empty((R, In), dtype=torch.float32, device=dev) if out is None else out
+    lam = torch.empty(R, dtype=torch.float64, device=dev) if lam is None else lam
+    nb = int(lib.fcs_als_workspace_bytes(R, In))
+    ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=dev) if ws is None else ws
+    ptrs = (ctypes.c_void_p * max(1, len(others)))(*[f.data_ptr() for f in others])
+    Is = (_I64 * max(1, len(others)))(*[int(f.shape[1]) for f in others])
+    C.check(lib.fcs_als_update(R, In, _ptr(Mt), len(others), ptrs, Is, _ptr(out), _ptr(lam), _ptr(ws),
+                               ctypes.c_size_t(ws.numel() * ws.element_size()), _stream(stream)))
+    return out, lam

@@ -13,16 +13,18 @@ For each component k:
     spectra are deflated by linearity:
     FCS(T - lam u o u o u) = FCS(T) - lam FCS(u o u o u).
 
-The starting vectors are inputs (the random draws of the method).  Vector
-normalisation, the argmax over starts and the subtraction of the deflation
-term are small elementwise steps done with torch on the device; every
-sketch and contraction runs in the library's kernels.
+The starting vectors are inputs (the random draws of the method).  Every
+step runs in the library's kernels: the sketches and contractions, the
+normalisation of the estimated vectors (fcs_normalize_rows), the choice of
+the best start (fcs_select_max, which leaves the chosen vector and its
+eigenvalue on the device) and the deflation (fcs_axpy); torch only holds
+the device memory, and the host reads the eigenvalues once at the end.
 """
 from __future__ import annotations
 
 import torch
 
-from .fcs import Plan
+from .fcs import Plan, axpy, normalize_rows, select_max
 
 
 def rtpm(plan: Plan, y: torch.Tensor, starts: torch.Tensor, iters: int, stream=None):
@@ -39,25 +41,21 @@ def rtpm(plan: Plan, y: torch.Tensor, starts: torch.Tensor, iters: int, stream=N
     with torch.cuda.stream(s):
         y = y.clone()
         spec = plan.spectrum(y, stream=s)
-        lams = []
+        lams = torch.empty(rank, dtype=torch.float64, device=y.device)
+        lam32 = torch.empty(rank, dtype=torch.float32, device=y.device)
         comps = torch.empty((rank, I), dtype=torch.float32, device=y.device)
         for k in range(rank):
-            U = starts[k].to(torch.float32)
-            U = (U / torch.linalg.vector_norm(U, dim=1, keepdim=True)).contiguous()
+            U = normalize_rows(starts[k].to(torch.float32).contiguous(), stream=s)
             for _ in range(iters):
                 W = plan.contract_free_mode(spec, 0, [None, U, U], stream=s)
-                U = (W / torch.linalg.vector_norm(W, dim=1, keepdim=True)).to(torch.float32).contiguous()
+                U = normalize_rows(W, stream=s)
             lam, _ = plan.contract_full(spec, [U, U, U], stream=s)
-            j = int(torch.argmax(lam).item())
-            lk = float(lam[j].item())
-            u = U[j:j + 1].contiguous()
-            lams.append(lk)
-            comps[k] = u[0]
-            lt = torch.tensor([lk], dtype=torch.float32, device=y.device)
-            yk, sk = plan.sketch_cp([u, u, u], lam=lt, want_spec=True, stream=s)
-            y -= yk
-            spec -= sk
-    return torch.tensor(lams, dtype=torch.float64), comps
+            u = comps[k:k + 1]
+            select_max(lam, U, row_out=u, val_out=lam32[k:k + 1], val64_out=lams[k:k + 1], stream=s)
+            yk, sk = plan.sketch_cp([u, u, u], lam=lam32[k:k + 1], want_spec=True, stream=s)
+            axpy(-1.0, yk, y, stream=s)
+            axpy(-1.0, sk, spec, stream=s)
+    return lams.cpu(), comps
 
 
 def rtpm_asym(plan: Plan, y: torch.Tensor, starts: torch.Tensor, iters: int, stream=None):
@@ -81,27 +79,22 @@ def rtpm_asym(plan: Plan, y: torch.Tensor, starts: torch.Tensor, iters: int, str
     with torch.cuda.stream(s):
         y = y.clone()
         spec = plan.spectrum(y, stream=s)
-        lams = []
+        lams = torch.empty(rank, dtype=torch.float64, device=y.device)
+        lam32 = torch.empty(rank, dtype=torch.float32, device=y.device)
         comps = [torch.empty((rank, plan.I[n]), dtype=torch.float32, device=y.device) for n in range(3)]
         for k in range(rank):
-            X = []
-            for n in range(3):
-                v = starts[k, :, n, :plan.I[n]].to(torch.float32)
-                X.append((v / torch.linalg.vector_norm(v, dim=1, keepdim=True)).contiguous())
+            X = [normalize_rows(starts[k, :, n, :plan.I[n]].to(torch.float32).contiguous(), stream=s)
+                 for n in range(3)]
             for _ in range(iters):
                 for n in range(3):
                     vecs = [None if m == n else X[m] for m in range(3)]
                     G = plan.contract_free_mode(spec, n, vecs, stream=s)
-                    X[n] = (G / torch.linalg.vector_norm(G, dim=1, keepdim=True)).to(torch.float32).contiguous()
+                    X[n] = normalize_rows(G, stream=s)
             lam, _ = plan.contract_full(spec, X, stream=s)
-            j = int(torch.argmax(lam).item())
-            lk = float(lam[j].item())
-            lams.append(lk)
-            x = [X[n][j:j + 1].contiguous() for n in range(3)]
+            x = [comps[n][k:k + 1] for n in range(3)]
             for n in range(3):
-                comps[n][k] = x[n][0]
-            lt = torch.tensor([lk], dtype=torch.float32, device=y.device)
-            yk, sk = plan.sketch_cp(x, lam=lt, want_spec=True, stream=s)
-            y -= yk
-            spec -= sk
-    return torch.tensor(lams, dtype=torch.float64), comps
+                select_max(lam, X[n], row_out=x[n], val_out=lam32[k:k + 1], val64_out=lams[k:k + 1], stream=s)
+            yk, sk = plan.sketch_cp(x, lam=lam32[k:k + 1], want_spec=True, stream=s)
+            axpy(-1.0, yk, y, stream=s)
+            axpy(-1.0, sk, spec, stream=s)
+    return lams.cpu(), comps
