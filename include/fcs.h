@@ -237,6 +237,15 @@ FCS_API fcs_status fcs_sketch_coo(fcs_plan_t plan, int64_t nnz, const int32_t *i
  *   out     device, float, D x J~; overwritten (may be NULL if spec is set)
  *   spec    device, float2 (re, im), D x fcs_plan_spec_len, or NULL; receives
  *           the spectrum of each sketch in the layout of fcs_plan_spec_len
+ *   ws      device workspace of at least fcs_workspace_bytes(FCS_OP_CP, R)
+ *           bytes: chunk partial spectra, slice terms and the maxima
+ *           max_i |U_n(i, r)| of the factor columns
+ * Precision: a count sketch of hash length J_n <= P is summed exactly in
+ * 64-bit fixed point scaled to its column maximum (each entry truncated by
+ * less than 2^(ceil(log2 I_n) - 61) times that maximum), then rounded once
+ * to float; a column holding NaN or Inf is summed in float instead.  Longer
+ * hashes (folded onto P positions) are float sums in bucket order.  The
+ * transforms, products and rank sums are float.
  * Errors: FCS_EINVAL, FCS_ENOMEM, FCS_EUNSUPPORTED, FCS_EDEVICE. */
 FCS_API fcs_status fcs_sketch_cp(fcs_plan_t plan, int64_t R, const float *const *U,
                          const float *lambda, float *out, float *spec,
@@ -245,12 +254,12 @@ FCS_API fcs_status fcs_sketch_cp(fcs_plan_t plan, int64_t R, const float *const 
 /* Allocation-free variant of fcs_sketch_cp, for callers that cannot
  * allocate device memory (code under HIP graph capture, tight serving
  * loops, harnesses that forbid hipMalloc).  Same arguments, results and
- * errors as fcs_sketch_cp except the workspace: the chunk partial spectra
- * and slice terms live in a device array of FCS_NOALLOC_SCRATCH_BYTES
+ * errors as fcs_sketch_cp except the workspace: the chunk partial spectra,
+ * slice terms and column maxima live in a device array of FCS_NOALLOC_SCRATCH_BYTES
  * inside the library (one per device, held until the process ends).  When
  * the partials of fcs_sketch_cp's rank chunks would not fit, fewer chunks
  * are used (the rank sums then group differently, a rounding-level
- * difference); a plan whose slice terms alone exceed the array fails with
+ * difference); a call whose slice terms and column maxima exceed the array fails with
  * FCS_ENOMEM before anything is enqueued.  The call makes no allocation.
  * All calls on one device share its array: calls that overlap on a device
  * (concurrent streams or threads) race and must be serialised by the

@@ -51,6 +51,30 @@ __global__ __launch_bounds__(Shape<P>::T) void cp_forward_kernel(CpDesc c) {
         store_partial<P>(c, d, q, chunk, acc);
 }
 
+// max_i |U_n(i, r)| of every factor column, at umax[n * R + r]: the scale of
+// the fixed-point count-sketch bins of the forward tiles.  A column that
+// holds a NaN or an infinity gets +inf (its sketch is then summed in float).
+__global__ __launch_bounds__(256) void column_absmax_kernel(CpDesc c, float *umax) {
+    __shared__ float part[4];
+    const int col = blockIdx.x;
+    const int n = col / c.R, r = col % c.R;
+    const int In = c.I[n];
+    const float *u = c.U[n] + (int64_t)r * In;
+    constexpr int K = 4;
+    float m = 0.f;
+    for (int i0 = threadIdx.x; i0 < In; i0 += K * 256) {
+        float a[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) a[k] = i0 + k * 256 < In ? fabsf(u[i0 + k * 256]) : 0.f;
+#pragma unroll
+        for (int k = 0; k < K; ++k) m = (a[k] != a[k]) ? INFINITY : fmaxf(m, a[k]);
+    }
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) umax[col] = fmaxf(fmaxf(part[0], part[1]), fmaxf(part[2], part[3]));
+}
+
 // Sum of the chunk partials of every (sketch, slice) into chunk slot 0, by
 // many workgroups (bandwidth bound): thread k of (d, q, block b) adds the
 // chunks of spectrum position b * 256 + k in chunk order.
@@ -347,6 +371,9 @@ void launch_cp(const CpDesc &c, hipStream_t s) {
     constexpr size_t lds = Lds<P>::bytes;
     allow_lds_cp(cp_forward_kernel<P>, lds);
     allow_lds_cp(cp_finalize_kernel<P>, lds);
+    if (c.umax)
+        hipLaunchKernelGGL(column_absmax_kernel, dim3((unsigned)(c.N * c.R)), dim3(256), 0, s, c,
+                           const_cast<float *>(c.umax));
     hipLaunchKernelGGL(cp_forward_kernel<P>, dim3(c.D * c.s.Qh * c.nchunks), dim3(Shape<P>::T), lds, s, c);
     if (c.nchunks > 1) {
         const int blocks = P / 256;
@@ -422,10 +449,15 @@ static size_t cp_ytmp_bytes(const fcs_plan *p) {
     return p->Qh > 1 ? align256((size_t)p->D * p->Qh * p->Jt * sizeof(float)) : 0;
 }
 
+// column maxima of the factors (fixed-point count-sketch scales)
+static size_t cp_umax_bytes(const fcs_plan *p, int64_t R) {
+    return align256((size_t)p->N * (size_t)std::max<int64_t>(R, 0) * sizeof(float));
+}
+
 size_t fcs_ws_cp(const fcs_plan *p, int64_t R) {
     if (p->P == 0) return 256;
     const int nch = cp_chunks(p, R);
-    return std::max<size_t>(256, cp_partial_bytes(p, nch) + cp_ytmp_bytes(p));
+    return std::max<size_t>(256, cp_partial_bytes(p, nch) + cp_ytmp_bytes(p) + cp_umax_bytes(p, R));
 }
 
 // factor sketches of a Kronecker or contraction plan whose 64-bit bins do
@@ -495,7 +527,8 @@ static fcs_status cp_check_args(const fcs_plan *p, int64_t R, const float *const
 }
 
 // The CP sketch with `nchunks` rank chunks; buf holds the chunk partial
-// spectra and the slice terms (cp_partial_bytes + cp_ytmp_bytes).
+// spectra, the slice terms and the column maxima (cp_partial_bytes +
+// cp_ytmp_bytes + cp_umax_bytes).
 static fcs_status cp_run(const fcs_plan *p, int64_t R, const float *const *U, const float *lambda, float *out,
                          float *spec, void *buf, int nchunks, hipStream_t s) {
     if (R == 0) {
@@ -516,6 +549,7 @@ static fcs_status cp_run(const fcs_plan *p, int64_t R, const float *const *U, co
     c.rchunk = (int)fcs_ceil_div(R, c.nchunks);
     c.partial = (float2 *)buf;
     c.ytmp = (float *)((char *)buf + cp_partial_bytes(p, c.nchunks));
+    c.umax = (const float *)((char *)buf + cp_partial_bytes(p, c.nchunks) + cp_ytmp_bytes(p));
     c.out = out;
     c.spec = (float2 *)spec;
     FCS_DISPATCH_FFT(p->P, (launch_cp<PP>(c, s)));
@@ -537,9 +571,10 @@ extern "C" fcs_status fcs_sketch_cp(fcs_plan_t p, int64_t R, const float *const 
 }
 
 // ---------------------------------------------------------------------------
-// Allocation-free CP sketch.  Its chunk partials and slice terms live in a
-// file-scope device array of FCS_NOALLOC_SCRATCH_BYTES (each device the
-// library runs on holds its own copy until the process ends).  Host code
+// Allocation-free CP sketch.  Its chunk partials, slice terms and column
+// maxima live in a file-scope device array of FCS_NOALLOC_SCRATCH_BYTES
+// (each device the library runs on holds its own copy until the process
+// ends).  Host code
 // never passes the array's name to a kernel: its device address is looked
 // up once per device with hipGetSymbolAddress on the first call made with
 // that device current, and kept.  Every call on a device shares that
@@ -577,10 +612,11 @@ extern "C" fcs_status fcs_sketch_cp_noalloc(fcs_plan_t p, int64_t R, const float
     // the rank chunks of fcs_sketch_cp, fewer when their partials would not
     // fit the array (the sums then group the ranks differently)
     int nch = R > 0 ? cp_chunks(p, R) : 1;
-    while (nch > 1 && cp_partial_bytes(p, nch) + cp_ytmp_bytes(p) > FCS_NOALLOC_SCRATCH_BYTES) --nch;
-    const size_t need = cp_partial_bytes(p, nch) + cp_ytmp_bytes(p);
+    const size_t fixed = cp_ytmp_bytes(p) + cp_umax_bytes(p, R);
+    while (nch > 1 && cp_partial_bytes(p, nch) + fixed > FCS_NOALLOC_SCRATCH_BYTES) --nch;
+    const size_t need = cp_partial_bytes(p, nch) + fixed;
     if (R > 0 && need > FCS_NOALLOC_SCRATCH_BYTES)
-        FCS_FAIL(FCS_ENOMEM, "slice terms need %zu bytes, more than the %zu-byte scratch array of "
+        FCS_FAIL(FCS_ENOMEM, "slice terms and column maxima need %zu bytes, more than the %zu-byte scratch array of "
                              "fcs_sketch_cp_noalloc (use fcs_sketch_cp with a workspace)",
                  need, (size_t)FCS_NOALLOC_SCRATCH_BYTES);
     void *buf = nullptr;

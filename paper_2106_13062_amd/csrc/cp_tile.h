@@ -180,6 +180,111 @@ __device__ __forceinline__ void build_cs_slice(float2 (&wv)[Shape<P>::E], const 
     }
 }
 
+// Slice q of the DFT of CS_n(u) for J_n <= P, built by scattering instead
+// of gathering: the thread clears its bucket positions t + eT of the bins
+// (the workgroup's LDS), every entry i of u is added to bucket h_n(i) with
+// sign s_n(i) by an LDS atomic (the I_n hash words and factor values are
+// coalesced loads), and the thread reads its positions back.  The loads and
+// VALU work scale with I_n instead of with the J_n bucket lists.
+//
+// Bins are 64-bit fixed point: with umax = max_i |u_i| < 2^e, every entry is
+// scaled by 2^F, F = 62 - ceil(log2 I_n) - e, so that no bucket sum can
+// reach 2^62, and added as an integer.  The sums are exact apart from the
+// truncation of each scaled entry to an integer (less than 2^-F, which is
+// at most 2^(ceil(log2 I_n) - 61) umax), and do not depend on the order of
+// the atomics; each bin is then read back through double precision and
+// rounded once to float.  A column with a non-finite entry (umax not
+// finite) is summed with float atomics instead, so infinities and NaNs
+// reach the sketch as in a float sum.  The LDS must be free on entry (no
+// thread still reading it); it is free again on return.
+template <int P>
+__device__ __forceinline__ void scatter_cs_slice(float2 (&wv)[Shape<P>::E], float2 *lds,
+                                                 const float *__restrict__ u,
+                                                 const uint32_t *__restrict__ words, int In, int Jn, int q,
+                                                 const SliceArgs &s, float scale, float umax) {
+    constexpr int T = Shape<P>::T;
+    constexpr int E = Shape<P>::E;
+    constexpr int K = 8;        // entries per thread whose loads are in flight together
+    static_assert(8 * P <= Lds<P>::bytes, "64-bit bins fit the transform's LDS");
+    const int t = tid_opaque();
+    unsigned long long *bins = reinterpret_cast<unsigned long long *>(lds);
+    float *fbins = reinterpret_cast<float *>(lds);
+    const bool fixed = umax <= 3.4028234e38f;       // false for inf and NaN
+    int F = 0;
+    if (fixed && umax > 0.f) {
+        int e = 0;
+        (void)frexpf(umax, &e);                      // umax < 2^e
+        const int lgI = In > 1 ? 32 - __clz(In - 1) : 0;
+        F = 62 - lgI - e;
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int j = t + e * T;
+        if (j < Jn) {
+            if (fixed) bins[j] = 0ull;
+            else fbins[j] = 0.f;
+        }
+    }
+    __syncthreads();
+    for (int i0 = t; i0 < In; i0 += K * T) {
+        uint32_t w[K];
+        float x[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int i = i0 + k * T;
+            w[k] = i < In ? words[i] : 0u;
+            x[k] = i < In ? u[i] : 0.f;
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (i0 + k * T >= In) continue;
+            const uint32_t h = w[k] & FCS_H_MASK;
+            const bool neg = (__float_as_uint(x[k]) ^ w[k]) & FCS_S_BIT;   // sign of s_n(i) u_i
+            if (fixed) {
+                // |u_i| 2^F < 2^62 split into exact 32-bit halves, then negated
+                // as a 64-bit integer when s_n(i) u_i < 0
+                const float a = ldexpf(fabsf(x[k]), F);
+                const float ahi = floorf(ldexpf(a, -32));
+                const float alo = fmaf(-ahi, 4294967296.0f, a);
+                unsigned long long v = ((unsigned long long)(uint32_t)ahi << 32) | (uint32_t)alo;
+                if (neg) v = 0ull - v;
+                __hip_atomic_fetch_add(bins + h, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            } else {
+                const float v = neg ? -fabsf(x[k]) : fabsf(x[k]);
+                __hip_atomic_fetch_add(fbins + h, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+        }
+    }
+    __syncthreads();
+    float y[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int j = t + e * T;
+        if (j >= Jn) {
+            y[e] = 0.f;
+        } else if (fixed) {
+            const unsigned long long b = bins[j];
+            const double v = fma((double)(int)(uint32_t)(b >> 32), 4294967296.0, (double)(uint32_t)b);
+            y[e] = (float)ldexp(v, -F);
+        } else {
+            y[e] = fbins[j];
+        }
+    }
+    __syncthreads();
+    // slice twist exp(-2 pi i q (t + eT) / L), factorised as in build_cs_slice
+    const float2 wt = (q == 0) ? make_float2(1.f, 0.f) : s.twL[q * t];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const float ys = y[e] * scale;
+        if (q == 0) {
+            wv[e] = make_float2(ys, 0.f);
+        } else {
+            const float2 w = cmul(wt, s.twL[q * e * T]);
+            wv[e] = make_float2(ys * w.x, ys * w.y);
+        }
+    }
+}
+
 // Slice q of the DFT of a dense real sequence y[0..M): the thread's
 // positions of w_q in registers (same factorised twist as the fold above).
 template <int P>
@@ -285,6 +390,8 @@ struct CpDesc {
                                      // rank chunks are chunks of the shared index
     float *out;                      // D x Jt or null
     float2 *spec;                    // D x (Qh * P) or null
+    const float *umax;               // CP: max_i |U_n(i, r)| at [n * R + r] (fixed-point scatter of the
+                                     // count sketches), or null (gather over the bucket lists)
     unsigned long long *kbins;       // KRON / CONTRACTION: 64-bit factor-sketch bins in global memory, laid
                                      // out like kscratch, when they exceed LDS (null: bins in LDS)
     int cnt_slice;                   // batch: first (d, q) chunk counter (nchunks > 1)
@@ -303,9 +410,11 @@ __device__ __forceinline__ void cp_tile(const CpDesc &c, int d, int q, int chunk
 #pragma unroll
     for (int e = 0; e < E; ++e) acc[e] = make_float2(0.f, 0.f);
     const int32_t *invd = c.inv + (int64_t)d * c.iblock;
-    // a factor column that fits in the (not yet used) LDS of the transform is
-    // first copied there with coalesced loads, so the gather's random reads
-    // of it are LDS reads instead of scattered global loads
+    // with the column maxima given, count sketches with J_n <= P are
+    // scattered into LDS bins; otherwise (and for J_n > P, folded onto P
+    // positions) they are gathered over the bucket lists, with a factor
+    // column that fits in the (not yet used) LDS of the transform first
+    // copied there, so the gather's random reads of it are LDS reads
     constexpr int LDS_FLOATS = 2 * Lds<P>::elems;
     float *lu = reinterpret_cast<float *>(lds);
     __syncthreads();
@@ -316,7 +425,10 @@ __device__ __forceinline__ void cp_tile(const CpDesc &c, int d, int q, int chunk
             const int32_t *off = invd + c.ioff[n];
             const float *un = c.U[n] + (int64_t)r * c.I[n];
             float2 v[E];
-            if (c.I[n] <= LDS_FLOATS) {
+            if (c.umax && c.J[n] <= P) {
+                scatter_cs_slice<P>(v, lds, un, c.tab + (int64_t)d * c.sumI + c.off[n], c.I[n], c.J[n], q, c.s,
+                                    n == 0 ? lam : 1.0f, c.umax[(int64_t)n * c.R + r]);
+            } else if (c.I[n] <= LDS_FLOATS) {
                 stage_column<T>(lu, un, c.I[n]);
                 __syncthreads();
                 build_cs_slice<P, EAGER2>(v, lu, off, off + c.J[n] + 1, off + c.J[n] + 1 + c.I[n], c.J[n], q, c.s,

@@ -196,3 +196,25 @@ def test_sketched_inner_products_are_unbiased_over_seeds():
     for k, v in est.items():
         v = np.asarray(v)
         assert abs(v.mean() - exact) <= 5 * v.std(ddof=1) / np.sqrt(v.size), (k, v.mean(), exact)
+
+
+def test_long_hash_count_sketch_baseline():
+    """The count sketch of vec(T) with one long hash pair (Definition 1; the
+    baseline of Sections 3 and 4.3, whose hash storage grows with prod I_n):
+    an order-1 plan over the 2.4e6 entries of the 30 x 40 x 40 x 50 Kronecker
+    set-up, J~ = 6e5 bins (compression ratio 4).  The sketch matches the
+    oracle's count sketch; decompression of the oracle's sketch (median over
+    D) is bit-exact on sampled entries."""
+    n, J, D, seed = 30 * 40 * 40 * 50, 600000, 3, 71
+    x = synth.dense_tensor(20, (n,))
+    plan = Plan((n,), (J,), D, seed, device=DEV)
+    got = plan.sketch_dense(dev(x)).cpu().numpy()
+    hs, ss = O.hash_tables(seed, D, (n,), (J,))
+    Y = np.stack([O.count_sketch(x, hs[d][0], ss[d][0], J) for d in range(D)])
+    for d in range(D):
+        assert rel(got[d], Y[d]) <= TOL, (d, rel(got[d], Y[d]))
+    Y32 = Y.astype(np.float32)
+    rec = plan.decompress(dev(Y32)).cpu().numpy()
+    k = np.random.default_rng(3).integers(0, n, 100_000)
+    want = O.decompress_at(Y32.astype(np.float64), hs, ss, [k]).astype(np.float32)
+    np.testing.assert_array_equal(rec[k], want)

@@ -63,6 +63,46 @@ def test_cp_sketch_parity(I, J, R, D, L):
         assert rel(y[d], want) <= TOL, (d, rel(y[d], want))
 
 
+def test_cp_sketch_wide_range_columns():
+    """Factor columns of very different scales (2^-8 .. 2^8), each with one
+    entry up to 2^24 times the rest, and one column whose other entries are
+    2^64 below its largest: the count sketches of the factor columns are
+    fixed-point sums scaled to each column's maximum, and the sketch still
+    matches the FP64 oracle to 1e-5 per sketch (entries more than about
+    2^(61 - log2 I_n) below their column's maximum are dropped, far below
+    that bar)."""
+    I, J, R, D, seed = (300, 200, 250), (256, 128, 512), 8, 3, 21
+    rng = np.random.default_rng(5)
+    U = synth.cp_factors(13, I, R)
+    for n, u in enumerate(U):
+        u *= np.float32(2.0) ** rng.integers(-8, 9, size=(1, R)).astype(np.float32)
+        rows = rng.integers(0, I[n], size=R)
+        u[rows, np.arange(R)] *= np.float32(2.0) ** rng.integers(0, 25, size=R).astype(np.float32)
+    U[0][:, 3] *= np.float32(2.0 ** -40)
+    U[0][17, 3] = np.float32(2.0 ** 24)
+    plan = Plan(I, J, D, seed, device=DEV)
+    y, _ = plan.sketch_cp(dev_factors(U))
+    y = y.cpu().numpy()
+    hs, ss = O.hash_tables(seed, D, I, J)
+    for d in range(D):
+        want = O.fcs_cp_conv(None, U, hs[d], ss[d], J)
+        assert rel(y[d], want) <= TOL, (d, rel(y[d], want))
+
+
+def test_cp_sketch_non_finite_column():
+    """A NaN in one factor column makes every entry of every sketch NaN (the
+    FFT spreads it over all bins), as a float sum does; the other sketches of
+    a call without it stay finite."""
+    I, J, R, D, seed = (50, 40, 30), (64, 32, 16), 4, 2, 8
+    U = synth.cp_factors(14, I, R)
+    plan = Plan(I, J, D, seed, device=DEV)
+    y0, _ = plan.sketch_cp(dev_factors(U))
+    assert np.isfinite(y0.cpu().numpy()).all()
+    U[1][7, 2] = np.nan
+    y, _ = plan.sketch_cp(dev_factors(U))
+    assert np.isnan(y.cpu().numpy()).all()
+
+
 def test_cp_matches_dense_of_materialised_tensor():
     """Section 3.1: the CP route equals the general-tensor formula on the
     materialised tensor (both on the GPU)."""
