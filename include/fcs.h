@@ -401,6 +401,10 @@ FCS_API fcs_status fcs_ts_fold(fcs_plan_t plan, const float *y, float *ts, void 
  *   vecs       host array of N device pointers; vecs[free_mode] is ignored
  *              (may be NULL), vecs[n] is P x I_n row-major float
  *   out        device, double, P x I_free row-major
+ *   ws         device workspace of at least fcs_workspace_bytes(FCS_OP_FREE_MODE,
+ *              0, P) bytes (z, the per-sketch estimates and the vector maxima)
+ * The count sketches of the vectors are formed as in fcs_sketch_cp (64-bit
+ * fixed point scaled to each vector's maximum for J_n <= P).
  * Errors: FCS_EINVAL, FCS_ENOMEM, FCS_EUNSUPPORTED, FCS_EDEVICE. */
 FCS_API fcs_status fcs_contract_free_mode(fcs_plan_t plan, const float *spec,
                                   int32_t free_mode, int64_t P,

@@ -51,28 +51,51 @@ __global__ __launch_bounds__(Shape<P>::T) void cp_forward_kernel(CpDesc c) {
         store_partial<P>(c, d, q, chunk, acc);
 }
 
-// max_i |U_n(i, r)| of every factor column, at umax[n * R + r]: the scale of
-// the fixed-point count-sketch bins of the forward tiles.  A column that
-// holds a NaN or an infinity gets +inf (its sketch is then summed in float).
-__global__ __launch_bounds__(256) void column_absmax_kernel(CpDesc c, float *umax) {
+// Columns whose maxima scale the fixed-point count-sketch bins: column r
+// of mode n is col[n][r * I[n] .. + I[n]) (modes with a null col are
+// skipped), r < ncols.
+struct ColMaxArgs {
+    const float *col[FCS_MAX_ORDER];
+    int I[FCS_MAX_ORDER];
+    int ncols;
+};
+
+// max_i |col_n(i, r)| of every column, at umax[n * ncols + r].  A column
+// that holds a NaN or an infinity gets +inf (its count sketch is then summed
+// in float).
+__global__ __launch_bounds__(256) void column_absmax_kernel(ColMaxArgs a, float *umax) {
     __shared__ float part[4];
-    const int col = blockIdx.x;
-    const int n = col / c.R, r = col % c.R;
-    const int In = c.I[n];
-    const float *u = c.U[n] + (int64_t)r * In;
+    const int idx = blockIdx.x;
+    const int n = idx / a.ncols, r = idx % a.ncols;
+    if (!a.col[n]) {
+        if (threadIdx.x == 0) umax[idx] = 0.f;
+        return;
+    }
+    const int In = a.I[n];
+    const float *u = a.col[n] + (int64_t)r * In;
     constexpr int K = 4;
     float m = 0.f;
     for (int i0 = threadIdx.x; i0 < In; i0 += K * 256) {
-        float a[K];
+        float v[K];
 #pragma unroll
-        for (int k = 0; k < K; ++k) a[k] = i0 + k * 256 < In ? fabsf(u[i0 + k * 256]) : 0.f;
+        for (int k = 0; k < K; ++k) v[k] = i0 + k * 256 < In ? fabsf(u[i0 + k * 256]) : 0.f;
 #pragma unroll
-        for (int k = 0; k < K; ++k) m = (a[k] != a[k]) ? INFINITY : fmaxf(m, a[k]);
+        for (int k = 0; k < K; ++k) m = (v[k] != v[k]) ? INFINITY : fmaxf(m, v[k]);
     }
     for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
     if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = m;
     __syncthreads();
-    if (threadIdx.x == 0) umax[col] = fmaxf(fmaxf(part[0], part[1]), fmaxf(part[2], part[3]));
+    if (threadIdx.x == 0) umax[idx] = fmaxf(fmaxf(part[0], part[1]), fmaxf(part[2], part[3]));
+}
+
+void launch_column_absmax(const float *const *col, const int *I, int N, int ncols, float *umax, hipStream_t s) {
+    ColMaxArgs a{};
+    for (int n = 0; n < N; ++n) {
+        a.col[n] = col[n];
+        a.I[n] = I[n];
+    }
+    a.ncols = ncols;
+    hipLaunchKernelGGL(column_absmax_kernel, dim3((unsigned)(N * ncols)), dim3(256), 0, s, a, umax);
 }
 
 // Sum of the chunk partials of every (sketch, slice) into chunk slot 0, by
@@ -185,6 +208,8 @@ struct FreeArgs {
     SliceArgs s;
     float *zbuf;            // [D][Pn][J_f]
     float *est;             // [Pn][I_f][D]
+    const float *umax;      // free mode: max_i |v_n(i)| of tuple p at [n * Pn + p] (fixed-point
+                            // scatter of the count sketches), or null (gather)
     double *full;           // full contraction: [Pn][D]
 };
 
@@ -209,7 +234,10 @@ __global__ __launch_bounds__(Shape<P>::T) void free_mode_kernel(FreeArgs a) {
             const int32_t *off = invd + a.ioff[n];
             const float *vn = a.vecs[n] + (int64_t)p * a.I[n];
             float2 F[E];
-            if (a.I[n] <= 2 * Lds<P>::elems) {
+            if (a.umax && a.J[n] <= P) {
+                scatter_cs_slice<P>(F, lds, vn, a.tab + (int64_t)d * a.sumI + a.off[n], a.I[n], a.J[n], q, a.s,
+                                    1.0f, a.umax[(int64_t)n * a.Pn + p]);
+            } else if (a.I[n] <= 2 * Lds<P>::elems) {
                 // the vector fits in the transform's (free) LDS: stage it
                 // there so the gather reads LDS, as in the CP tiles
                 float *lv = reinterpret_cast<float *>(lds);
@@ -371,9 +399,7 @@ void launch_cp(const CpDesc &c, hipStream_t s) {
     constexpr size_t lds = Lds<P>::bytes;
     allow_lds_cp(cp_forward_kernel<P>, lds);
     allow_lds_cp(cp_finalize_kernel<P>, lds);
-    if (c.umax)
-        hipLaunchKernelGGL(column_absmax_kernel, dim3((unsigned)(c.N * c.R)), dim3(256), 0, s, c,
-                           const_cast<float *>(c.umax));
+    if (c.umax) launch_column_absmax(c.U, c.I, c.N, c.R, const_cast<float *>(c.umax), s);
     hipLaunchKernelGGL(cp_forward_kernel<P>, dim3(c.D * c.s.Qh * c.nchunks), dim3(Shape<P>::T), lds, s, c);
     if (c.nchunks > 1) {
         const int blocks = P / 256;
@@ -506,7 +532,8 @@ size_t fcs_ws_free_mode(const fcs_plan *p, int64_t Pn) {
         Jmax = std::max<int64_t>(Jmax, p->J[n]);
         Imax = std::max<int64_t>(Imax, p->I[n]);
     }
-    return align256((size_t)p->D * Pn * Jmax * 4) + align256((size_t)Pn * Imax * p->D * 4);
+    return align256((size_t)p->D * Pn * Jmax * 4) + align256((size_t)Pn * Imax * p->D * 4) +
+           align256((size_t)p->N * Pn * 4);
 }
 
 // Argument checks shared by fcs_sketch_cp and fcs_sketch_cp_noalloc
@@ -749,7 +776,12 @@ extern "C" fcs_status fcs_contract_free_mode(fcs_plan_t p, const float *spec, in
     fa.s = slice_args(p);
     fa.zbuf = (float *)ws;
     fa.est = (float *)((char *)ws + align256((size_t)p->D * Pn * Jmax * 4));
+    int64_t Imax = 0;
+    for (int n = 0; n < p->N; ++n) Imax = std::max<int64_t>(Imax, p->I[n]);
+    float *vmax = (float *)((char *)fa.est + align256((size_t)Pn * Imax * p->D * 4));
+    fa.umax = vmax;
     hipStream_t s = (hipStream_t)stream;
+    launch_column_absmax(fa.vecs, fa.I, p->N, (int)Pn, vmax, s);
     FCS_DISPATCH_FFT(p->P, (launch_free<PP>(fa, s)));
     FCS_LAUNCH_CHECK();
     const int64_t rows = Pn * p->I[free_mode];
