@@ -18,6 +18,11 @@
 // rows in slice order.  Counters and queue heads are reset by the kernels
 // themselves (the last finisher), so a captured graph replays without any
 // memset node.
+//
+// Count sketches.  CP tiles scatter each factor column into fixed-point LDS
+// bins scaled to the column's maximum; one small kernel at the head of the
+// run (and of the graph) computes the maxima of every CP item's columns,
+// one wave per column.
 #include "fcs_internal.h"
 
 #include <algorithm>
@@ -129,6 +134,44 @@ __global__ __launch_bounds__(Shape<P>::T) void batch_kernel(BatchArgs a) {
     }
 }
 
+// Column maxima of every CP item's factors (the scales of the fixed-point
+// count-sketch bins of its tiles), one wave per column.  Entry k covers the
+// R columns of one (item, mode); its columns are the global column indices
+// [first, first + R) and its maxima go to ws + out_off + r (floats).
+struct AbsmaxEntry {
+    const float *U;
+    int64_t first;
+    int64_t out_off;                 // in floats from the workspace base
+    int I, R;
+};
+
+__global__ __launch_bounds__(256) void batch_absmax_kernel(const AbsmaxEntry *ent, int nent, int64_t ncols,
+                                                           float *base) {
+    const int64_t g = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (g >= ncols) return;
+    int lo = 0, hi = nent - 1;                   // last entry with first <= g
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (ent[mid].first <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    const AbsmaxEntry e = ent[lo];
+    const int64_t r = g - e.first;
+    const float *u = e.U + r * e.I;
+    constexpr int K = 8;
+    float m = 0.f;
+    for (int i0 = lane; i0 < e.I; i0 += K * 64) {
+        float v[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] = i0 + k * 64 < e.I ? fabsf(u[i0 + k * 64]) : 0.f;
+#pragma unroll
+        for (int k = 0; k < K; ++k) m = (v[k] != v[k]) ? INFINITY : fmaxf(m, v[k]);
+    }
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+    if (lane == 0) base[e.out_off + r] = m;
+}
+
 template <typename K>
 void allow_lds_batch(K kernel, size_t bytes) {
     fcs_allow_lds(reinterpret_cast<const void *>(kernel), bytes);
@@ -159,7 +202,10 @@ struct fcs_batch {
         int grid = 0;
     };
     std::vector<CpDesc> desc;            // device pointers patched at prepare
-    std::vector<size_t> part_off, ytmp_off, kscr_off;
+    std::vector<size_t> part_off, ytmp_off, kscr_off, umax_off;
+    std::vector<AbsmaxEntry> absmax;     // column-max work, out_off patched at create
+    size_t absmax_off = 0, umax_base = 0;
+    int64_t absmax_cols = 0;
     std::vector<int> zero_items;         // CP items of rank 0
     Cls cls[NCLASS];
     size_t desc_off = 0, ctr_off = 0, total = 0;
@@ -209,6 +255,15 @@ fcs_status launch_all(fcs_batch *b, char *ws, hipStream_t main, bool fork) {
             fcs_status st = fcs_zero_fill(reinterpret_cast<float *>(c.spec), (int64_t)c.D * c.s.Qh * c.s.P * 2, main);
             if (st != FCS_OK) return st;
         }
+    }
+    if (b->absmax_cols > 0) {
+        const unsigned grid = (unsigned)fcs_ceil_div(b->absmax_cols, 4);
+        hipLaunchKernelGGL(batch_absmax_kernel, dim3(grid), dim3(256), 0, main,
+                           reinterpret_cast<const AbsmaxEntry *>(ws + b->absmax_off), (int)b->absmax.size(),
+                           b->absmax_cols, reinterpret_cast<float *>(ws));
+        FCS_LAUNCH_CHECK();
+        // the class kernels (forked from ev[0] under capture) start after it
+        if (fork) FCS_HIP_CHECK(hipEventRecord(b->ev[0], main));
     }
     int k = 0;
     for (int ci = 0; ci < NCLASS; ++ci) {
@@ -266,7 +321,7 @@ extern "C" fcs_status fcs_batch_create(const fcs_batch_item *items, int64_t coun
         c.out = it.out;
         c.spec = reinterpret_cast<float2 *>(it.spec);
         const double lg = std::log2((double)p->P);
-        size_t part = 0, ytmp = 0, kscr = 0;
+        size_t part = 0, ytmp = 0, kscr = 0, umax = 0;
         if (it.kind == FCS_ITEM_KRON) {
             if (p->N != 4) return fail((fcs_set_error("item %lld: Kronecker item needs N=4", (long long)i), FCS_EINVAL));
             if (!it.U[0] || !it.U[1]) return fail((fcs_set_error("item %lld: null factor matrix", (long long)i), FCS_EINVAL));
@@ -300,7 +355,11 @@ extern "C" fcs_status fcs_batch_create(const fcs_batch_item *items, int64_t coun
                 for (int n = 0; n < p->N; ++n) {
                     if (!it.U[n]) return fail((fcs_set_error("item %lld: null factor %d", (long long)i, n), FCS_EINVAL));
                     c.U[n] = it.U[n];
+                    // out_off is the item-relative offset until the layout is known
+                    b->absmax.push_back({it.U[n], b->absmax_cols, (int64_t)n * it.R, (int)p->I[n], (int)it.R});
+                    b->absmax_cols += it.R;
                 }
+                umax = (size_t)p->N * it.R * sizeof(float);
                 c.rchunk = (int)std::min<int64_t>(it.R, std::max<int64_t>(1, fcs_ceil_div(tile_ffts, p->N)));
                 c.nchunks = (int)fcs_ceil_div(it.R, c.rchunk);
                 double per_rank = 0.0;
@@ -332,6 +391,7 @@ extern "C" fcs_status fcs_batch_create(const fcs_batch_item *items, int64_t coun
         b->part_off.push_back(part);
         b->ytmp_off.push_back(ytmp);
         b->kscr_off.push_back(kscr);
+        b->umax_off.push_back(umax);
     }
     // costliest tiles first in every class
     const int cus = fcs_device_cu_count();
@@ -367,6 +427,20 @@ extern "C" fcs_status fcs_batch_create(const fcs_batch_item *items, int64_t coun
         b->kscr_off[i] = ko ? cur : 0;
         cur = align256(cur + ko);
     }
+    // column maxima of the CP items (4-byte aligned, packed) and the
+    // column-max work list
+    b->umax_base = cur;
+    for (size_t i = 0, e = 0; i < b->desc.size(); ++i) {
+        const size_t uo = b->umax_off[i];
+        b->umax_off[i] = uo ? cur : 0;
+        if (uo) {
+            for (int n = 0; n < b->desc[i].N; ++n, ++e) b->absmax[e].out_off += (int64_t)(cur / sizeof(float));
+        }
+        cur += uo;
+    }
+    cur = align256(cur);
+    b->absmax_off = cur;
+    cur = align256(cur + b->absmax.size() * sizeof(AbsmaxEntry));
     b->total = std::max<size_t>(cur, 256);
     *out = b;
     return FCS_OK;
@@ -394,7 +468,11 @@ extern "C" fcs_status fcs_batch_prepare(fcs_batch_t b, void *ws, size_t ws_bytes
         b->desc[i].partial = b->part_off[i] ? reinterpret_cast<float2 *>(w + b->part_off[i]) : nullptr;
         b->desc[i].ytmp = b->ytmp_off[i] ? reinterpret_cast<float *>(w + b->ytmp_off[i]) : nullptr;
         b->desc[i].kscratch = b->kscr_off[i] ? reinterpret_cast<float *>(w + b->kscr_off[i]) : nullptr;
+        b->desc[i].umax = b->umax_off[i] ? reinterpret_cast<const float *>(w + b->umax_off[i]) : nullptr;
     }
+    if (!b->absmax.empty())
+        FCS_HIP_CHECK(hipMemcpyAsync(w + b->absmax_off, b->absmax.data(), b->absmax.size() * sizeof(AbsmaxEntry),
+                                     hipMemcpyHostToDevice, s));
     if (!b->desc.empty())
         FCS_HIP_CHECK(hipMemcpyAsync(w + b->desc_off, b->desc.data(), b->desc.size() * sizeof(CpDesc),
                                      hipMemcpyHostToDevice, s));
