@@ -135,13 +135,16 @@ __global__ __launch_bounds__(Shape<P>::T) void batch_kernel(BatchArgs a) {
 }
 
 // Column maxima of every CP item's factors (the scales of the fixed-point
-// count-sketch bins of its tiles), one wave per column.  Entry k covers the
-// R columns of one (item, mode); its columns are the global column indices
-// [first, first + R) and its maxima go to ws + out_off + r (floats).
+// count-sketch bins of its tiles) and the exponents of their norms (the
+// scales of two modes packed into one transform), one wave per column.
+// Entry k covers the R columns of one (item, mode); its columns are the
+// global column indices [first, first + R), their maxima go to
+// ws + out_off + r and their exponents to ws + out_off + exp_gap + r (floats).
 struct AbsmaxEntry {
     const float *U;
     int64_t first;
     int64_t out_off;                 // in floats from the workspace base
+    int64_t exp_gap;                 // N R of the item
     int I, R;
 };
 
@@ -161,15 +164,27 @@ __global__ __launch_bounds__(256) void batch_absmax_kernel(const AbsmaxEntry *en
     const float *u = e.U + r * e.I;
     constexpr int K = 8;
     float m = 0.f;
+    double sq = 0.0;
     for (int i0 = lane; i0 < e.I; i0 += K * 64) {
         float v[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) v[k] = i0 + k * 64 < e.I ? fabsf(u[i0 + k * 64]) : 0.f;
 #pragma unroll
-        for (int k = 0; k < K; ++k) m = (v[k] != v[k]) ? INFINITY : fmaxf(m, v[k]);
+        for (int k = 0; k < K; ++k) {
+            m = (v[k] != v[k]) ? INFINITY : fmaxf(m, v[k]);
+            sq += (double)v[k] * (double)v[k];
+        }
     }
-    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
-    if (lane == 0) base[e.out_off + r] = m;
+    for (int o = 32; o > 0; o >>= 1) {
+        m = fmaxf(m, __shfl_xor(m, o));
+        sq += __shfl_xor(sq, o);
+    }
+    if (lane == 0) {
+        int ex = 0;
+        if (m <= 3.4028234e38f && sq > 0.0) (void)frexp(sqrt(sq), &ex);
+        base[e.out_off + r] = m;
+        base[e.out_off + e.exp_gap + r] = (float)ex;
+    }
 }
 
 template <typename K>
@@ -356,10 +371,11 @@ extern "C" fcs_status fcs_batch_create(const fcs_batch_item *items, int64_t coun
                     if (!it.U[n]) return fail((fcs_set_error("item %lld: null factor %d", (long long)i, n), FCS_EINVAL));
                     c.U[n] = it.U[n];
                     // out_off is the item-relative offset until the layout is known
-                    b->absmax.push_back({it.U[n], b->absmax_cols, (int64_t)n * it.R, (int)p->I[n], (int)it.R});
+                    b->absmax.push_back({it.U[n], b->absmax_cols, (int64_t)n * it.R, (int64_t)p->N * it.R,
+                                         (int)p->I[n], (int)it.R});
                     b->absmax_cols += it.R;
                 }
-                umax = (size_t)p->N * it.R * sizeof(float);
+                umax = 2 * (size_t)p->N * it.R * sizeof(float);
                 c.rchunk = (int)std::min<int64_t>(it.R, std::max<int64_t>(1, fcs_ceil_div(tile_ffts, p->N)));
                 c.nchunks = (int)fcs_ceil_div(it.R, c.rchunk);
                 double per_rank = 0.0;
@@ -469,6 +485,7 @@ extern "C" fcs_status fcs_batch_prepare(fcs_batch_t b, void *ws, size_t ws_bytes
         b->desc[i].ytmp = b->ytmp_off[i] ? reinterpret_cast<float *>(w + b->ytmp_off[i]) : nullptr;
         b->desc[i].kscratch = b->kscr_off[i] ? reinterpret_cast<float *>(w + b->kscr_off[i]) : nullptr;
         b->desc[i].umax = b->umax_off[i] ? reinterpret_cast<const float *>(w + b->umax_off[i]) : nullptr;
+        b->desc[i].uexp = b->desc[i].umax ? b->desc[i].umax + (int64_t)b->desc[i].N * b->desc[i].R : nullptr;
     }
     if (!b->absmax.empty())
         FCS_HIP_CHECK(hipMemcpyAsync(w + b->absmax_off, b->absmax.data(), b->absmax.size() * sizeof(AbsmaxEntry),

@@ -62,40 +62,66 @@ struct ColMaxArgs {
 
 // max_i |col_n(i, r)| of every column, at umax[n * ncols + r].  A column
 // that holds a NaN or an infinity gets +inf (its count sketch is then summed
-// in float).
-__global__ __launch_bounds__(256) void column_absmax_kernel(ColMaxArgs a, float *umax) {
+// in float).  With uexp given, uexp[n * ncols + r] receives the exponent e
+// with 2^(e-1) <= ||col_n(:, r)|| < 2^e (0 for a zero or non-finite column),
+// the power-of-two scale that balances two modes packed into one transform.
+__global__ __launch_bounds__(256) void column_absmax_kernel(ColMaxArgs a, float *umax, float *uexp) {
     __shared__ float part[4];
+    __shared__ double psq[4];
     const int idx = blockIdx.x;
     const int n = idx / a.ncols, r = idx % a.ncols;
     if (!a.col[n]) {
-        if (threadIdx.x == 0) umax[idx] = 0.f;
+        if (threadIdx.x == 0) {
+            umax[idx] = 0.f;
+            if (uexp) uexp[idx] = 0.f;
+        }
         return;
     }
     const int In = a.I[n];
     const float *u = a.col[n] + (int64_t)r * In;
     constexpr int K = 4;
     float m = 0.f;
+    double sq = 0.0;
     for (int i0 = threadIdx.x; i0 < In; i0 += K * 256) {
         float v[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) v[k] = i0 + k * 256 < In ? fabsf(u[i0 + k * 256]) : 0.f;
 #pragma unroll
-        for (int k = 0; k < K; ++k) m = (v[k] != v[k]) ? INFINITY : fmaxf(m, v[k]);
+        for (int k = 0; k < K; ++k) {
+            m = (v[k] != v[k]) ? INFINITY : fmaxf(m, v[k]);
+            sq += (double)v[k] * (double)v[k];
+        }
     }
-    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
-    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = m;
+    for (int o = 32; o > 0; o >>= 1) {
+        m = fmaxf(m, __shfl_xor(m, o));
+        sq += __shfl_xor(sq, o);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        part[threadIdx.x >> 6] = m;
+        psq[threadIdx.x >> 6] = sq;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) umax[idx] = fmaxf(fmaxf(part[0], part[1]), fmaxf(part[2], part[3]));
+    if (threadIdx.x == 0) {
+        const float mx = fmaxf(fmaxf(part[0], part[1]), fmaxf(part[2], part[3]));
+        umax[idx] = mx;
+        if (uexp) {
+            const double nrm = sqrt(psq[0] + psq[1] + psq[2] + psq[3]);
+            int e = 0;
+            if (mx <= 3.4028234e38f && nrm > 0.0) (void)frexp(nrm, &e);
+            uexp[idx] = (float)e;
+        }
+    }
 }
 
-void launch_column_absmax(const float *const *col, const int *I, int N, int ncols, float *umax, hipStream_t s) {
+void launch_column_absmax(const float *const *col, const int *I, int N, int ncols, float *umax, float *uexp,
+                          hipStream_t s) {
     ColMaxArgs a{};
     for (int n = 0; n < N; ++n) {
         a.col[n] = col[n];
         a.I[n] = I[n];
     }
     a.ncols = ncols;
-    hipLaunchKernelGGL(column_absmax_kernel, dim3((unsigned)(N * ncols)), dim3(256), 0, s, a, umax);
+    hipLaunchKernelGGL(column_absmax_kernel, dim3((unsigned)(N * ncols)), dim3(256), 0, s, a, umax, uexp);
 }
 
 // Sum of the chunk partials of every (sketch, slice) into chunk slot 0, by
@@ -399,7 +425,7 @@ void launch_cp(const CpDesc &c, hipStream_t s) {
     constexpr size_t lds = Lds<P>::bytes;
     allow_lds_cp(cp_forward_kernel<P>, lds);
     allow_lds_cp(cp_finalize_kernel<P>, lds);
-    if (c.umax) launch_column_absmax(c.U, c.I, c.N, c.R, const_cast<float *>(c.umax), s);
+    if (c.umax) launch_column_absmax(c.U, c.I, c.N, c.R, const_cast<float *>(c.umax), const_cast<float *>(c.uexp), s);
     hipLaunchKernelGGL(cp_forward_kernel<P>, dim3(c.D * c.s.Qh * c.nchunks), dim3(Shape<P>::T), lds, s, c);
     if (c.nchunks > 1) {
         const int blocks = P / 256;
@@ -475,9 +501,10 @@ static size_t cp_ytmp_bytes(const fcs_plan *p) {
     return p->Qh > 1 ? align256((size_t)p->D * p->Qh * p->Jt * sizeof(float)) : 0;
 }
 
-// column maxima of the factors (fixed-point count-sketch scales)
+// column maxima of the factors (fixed-point count-sketch scales) and their
+// norm exponents (scales of the modes packed into one transform)
 static size_t cp_umax_bytes(const fcs_plan *p, int64_t R) {
-    return align256((size_t)p->N * (size_t)std::max<int64_t>(R, 0) * sizeof(float));
+    return align256(2 * (size_t)p->N * (size_t)std::max<int64_t>(R, 0) * sizeof(float));
 }
 
 size_t fcs_ws_cp(const fcs_plan *p, int64_t R) {
@@ -577,6 +604,7 @@ static fcs_status cp_run(const fcs_plan *p, int64_t R, const float *const *U, co
     c.partial = (float2 *)buf;
     c.ytmp = (float *)((char *)buf + cp_partial_bytes(p, c.nchunks));
     c.umax = (const float *)((char *)buf + cp_partial_bytes(p, c.nchunks) + cp_ytmp_bytes(p));
+    c.uexp = c.umax + (int64_t)p->N * R;
     c.out = out;
     c.spec = (float2 *)spec;
     FCS_DISPATCH_FFT(p->P, (launch_cp<PP>(c, s)));
@@ -781,7 +809,7 @@ extern "C" fcs_status fcs_contract_free_mode(fcs_plan_t p, const float *spec, in
     float *vmax = (float *)((char *)fa.est + align256((size_t)Pn * Imax * p->D * 4));
     fa.umax = vmax;
     hipStream_t s = (hipStream_t)stream;
-    launch_column_absmax(fa.vecs, fa.I, p->N, (int)Pn, vmax, s);
+    launch_column_absmax(fa.vecs, fa.I, p->N, (int)Pn, vmax, nullptr, s);
     FCS_DISPATCH_FFT(p->P, (launch_free<PP>(fa, s)));
     FCS_LAUNCH_CHECK();
     const int64_t rows = Pn * p->I[free_mode];

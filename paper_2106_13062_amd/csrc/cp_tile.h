@@ -196,8 +196,10 @@ __device__ __forceinline__ void build_cs_slice(float2 (&wv)[Shape<P>::E], const 
 // rounded once to float.  A column with a non-finite entry (umax not
 // finite) is summed with float atomics instead, so infinities and NaNs
 // reach the sketch as in a float sum.  The LDS must be free on entry (no
-// thread still reading it); it is free again on return.
-template <int P>
+// thread still reading it); it is free again on return.  IMAG adds i times
+// the slice to wv instead of overwriting it (two real sequences packed into
+// one complex transform).
+template <int P, bool IMAG = false>
 __device__ __forceinline__ void scatter_cs_slice(float2 (&wv)[Shape<P>::E], float2 *lds,
                                                  const float *__restrict__ u,
                                                  const uint32_t *__restrict__ words, int In, int Jn, int q,
@@ -276,13 +278,45 @@ __device__ __forceinline__ void scatter_cs_slice(float2 (&wv)[Shape<P>::E], floa
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const float ys = y[e] * scale;
+        float2 v;
         if (q == 0) {
-            wv[e] = make_float2(ys, 0.f);
+            v = make_float2(ys, 0.f);
         } else {
             const float2 w = cmul(wt, s.twL[q * e * T]);
-            wv[e] = make_float2(ys * w.x, ys * w.y);
+            v = make_float2(ys * w.x, ys * w.y);
         }
+        if (IMAG) wv[e] = make_float2(wv[e].x - v.y, wv[e].y + v.x);
+        else wv[e] = v;
     }
+}
+
+// Slices q = 0 and, Q even, q = Q/2 hold conjugate-symmetric spectra of a
+// real sequence: with X the L-point DFT, conj(X[Qk + q]) = X[Qk' + q] for
+// k' = (P - k) mod P (q = 0) or k' = P - 1 - k (q = Q/2).  Two real
+// sequences a, b then share one P-point transform Z of the slice of a + i b:
+// F(a)[k] = (Z[k] + conj(Z[k'])) / 2 and F(b)[k] = (Z[k] - conj(Z[k'])) / 2i.
+// Given the thread's Z[t + eT] in z, returns F(a)[k] F(b)[k] at the same
+// positions (the two modes' product) times 2^eab through one exchange in
+// LDS (free on entry and on return).
+template <int P>
+__device__ __forceinline__ void split_pair_product(float2 (&z)[Shape<P>::E], float2 *lds, bool half, int eab) {
+    constexpr int T = Shape<P>::T;
+    constexpr int E = Shape<P>::E;
+    store<P>(lds, z);
+    __syncthreads();
+    const int t = tid_opaque();
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int k = t + e * T;
+        const int km = half ? P - 1 - k : (P - k) & (P - 1);
+        const float2 m = lds[pad(km)];
+        // 2 F(a) = (zr + mr, zi - mi), 2 F(b) = (zi + mi, mr - zr)
+        const float2 a = make_float2(z[e].x + m.x, z[e].y - m.y);
+        const float2 b = make_float2(z[e].y + m.y, m.x - z[e].x);
+        const float2 ab = cmul(a, b);
+        z[e] = make_float2(ldexpf(ab.x, eab - 2), ldexpf(ab.y, eab - 2));
+    }
+    __syncthreads();
 }
 
 // Slice q of the DFT of a dense real sequence y[0..M): the thread's
@@ -392,6 +426,8 @@ struct CpDesc {
     float2 *spec;                    // D x (Qh * P) or null
     const float *umax;               // CP: max_i |U_n(i, r)| at [n * R + r] (fixed-point scatter of the
                                      // count sketches), or null (gather over the bucket lists)
+    const float *uexp;               // CP: e with 2^(e-1) <= ||U_n(:, r)|| < 2^e at [n * R + r] (scales of
+                                     // two modes packed into one transform), or null (no packing)
     unsigned long long *kbins;       // KRON / CONTRACTION: 64-bit factor-sketch bins in global memory, laid
                                      // out like kscratch, when they exceed LDS (null: bins in LDS)
     int cnt_slice;                   // batch: first (d, q) chunk counter (nchunks > 1)
@@ -418,6 +454,9 @@ __device__ __forceinline__ void cp_tile(const CpDesc &c, int d, int q, int chunk
     constexpr int LDS_FLOATS = 2 * Lds<P>::elems;
     float *lu = reinterpret_cast<float *>(lds);
     __syncthreads();
+    // slices 0 and Q/2 are conjugate-symmetric: there two modes' count
+    // sketches share one transform (split_pair_product)
+    const bool selfconj = (q == 0) || (2 * q == c.s.Q);
     for (int r = r0; r < r1; ++r) {
         float2 prod[E];
         const float lam = c.lambda ? c.lambda[r] : 1.0f;
@@ -425,6 +464,29 @@ __device__ __forceinline__ void cp_tile(const CpDesc &c, int d, int q, int chunk
             const int32_t *off = invd + c.ioff[n];
             const float *un = c.U[n] + (int64_t)r * c.I[n];
             float2 v[E];
+            if (selfconj && c.uexp && n + 1 < c.N && c.J[n] <= P && c.J[n + 1] <= P) {
+                // both columns scaled to norms in [1/2, 1) so that the
+                // rounding of the shared transform is relative to each
+                // mode's own size; the product is scaled back exactly
+                const int ea = (int)c.uexp[(int64_t)n * c.R + r];
+                const int eb = (int)c.uexp[(int64_t)(n + 1) * c.R + r];
+                scatter_cs_slice<P>(v, lds, un, c.tab + (int64_t)d * c.sumI + c.off[n], c.I[n], c.J[n], q, c.s,
+                                    ldexpf(n == 0 ? lam : 1.0f, -ea), c.umax[(int64_t)n * c.R + r]);
+                scatter_cs_slice<P, true>(v, lds, c.U[n + 1] + (int64_t)r * c.I[n + 1],
+                                          c.tab + (int64_t)d * c.sumI + c.off[n + 1], c.I[n + 1], c.J[n + 1], q,
+                                          c.s, ldexpf(1.0f, -eb), c.umax[(int64_t)(n + 1) * c.R + r]);
+                forward_regs<P>(lds, c.s.twP, v);
+                split_pair_product<P>(v, lds, q != 0, ea + eb);
+                if (n == 0) {
+#pragma unroll
+                    for (int e = 0; e < E; ++e) prod[e] = v[e];
+                } else {
+#pragma unroll
+                    for (int e = 0; e < E; ++e) prod[e] = cmul(prod[e], v[e]);
+                }
+                ++n;
+                continue;
+            }
             if (c.umax && c.J[n] <= P) {
                 scatter_cs_slice<P>(v, lds, un, c.tab + (int64_t)d * c.sumI + c.off[n], c.I[n], c.J[n], q, c.s,
                                     n == 0 ? lam : 1.0f, c.umax[(int64_t)n * c.R + r]);
