@@ -1,8 +1,9 @@
 """Sketched alternating least squares on the GPU (Section 4.1.2, ALS) against the
 FP64 oracle run on the same inputs: same tensor, same hash tables (the
-plan's), same starting factors.  Every weight agrees to 1e-4 relative and
-every factor column to 1 - |cos| <= 1e-4; both recover the planted
-factors."""
+plan's), same starting factors.  Every weight agrees to 1e-5 relative (the
+bar of a single FP32 contraction; measured maxima are below 1e-6) and every
+factor column to 1 - |cos| <= 1e-9 (quadratic in the angle, about 1e-12
+measured); both recover the planted factors."""
 import numpy as np
 import pytest
 import torch
@@ -35,10 +36,12 @@ def test_als_matches_oracle(I, J, D, w, noise, iters, tseed, hseed, iseed):
     T = Tv.astype(np.float32).astype(np.float64).reshape((I, I, I), order="F")
     Y = np.stack([O.fcs_dense(T, hs[d], ss[d], (J, J, J)) for d in range(D)])
     lam_o, G_o = O.als(Y, hs, ss, (J, J, J), init, iters)
-    assert np.all(np.abs(lam_g - lam_o) <= 1e-4 * np.abs(lam_o)), (lam_g, lam_o)
+    print(f"max relative weight difference {np.max(np.abs(lam_g - lam_o) / np.abs(lam_o)):.3e}", flush=True)
+    assert np.all(np.abs(lam_g - lam_o) <= 1e-5 * np.abs(lam_o)), (lam_g, lam_o)
     for n in range(3):
         cos = np.abs(np.sum(G_g[n] * G_o[n], axis=0)) / np.linalg.norm(G_g[n], axis=0)
-        assert np.all(1.0 - cos <= 1e-4), (n, cos)
+        print(f"mode {n}: max 1 - |cos| {np.max(1.0 - cos):.3e}", flush=True)
+        assert np.all(1.0 - cos <= 1e-9), (n, cos)
         assert np.all(np.abs(G_g[n].T @ F[n]).max(axis=1) >= 0.99)
 
 

@@ -1,7 +1,10 @@
 """Sketched robust tensor power method on the GPU (Section 4.1.1, RTPM) against
 the FP64 oracle run on the same inputs: same tensor, same hash tables (the
-plan's), same starting vectors.  Every eigenvalue agrees to 1e-4 relative
-and every component to 1 - |<u_gpu, u_oracle>| <= 1e-4."""
+plan's), same starting vectors.  Every eigenvalue agrees to 1e-5 relative
+(the bar of a single FP32 contraction: the power iterations do not amplify
+the contractions' rounding, measured maxima are below 1e-6) and every
+component to 1 - |<u_gpu, u_oracle>| <= 1e-9 (1 - cos is quadratic in the
+angle, about 1e-12 measured)."""
 import numpy as np
 import pytest
 import torch
@@ -33,9 +36,11 @@ def test_rtpm_matches_oracle(I, J, D, w, noise, L, iters):
     T = Tv.astype(np.float32).astype(np.float64).reshape((I, I, I), order="F")
     Y = np.stack([O.fcs_dense(T, hs[d], ss[d], (J, J, J)) for d in range(D)])
     lam_o, U_o = O.rtpm(Y, hs, ss, (J, J, J), R, starts, iters)
-    assert np.all(np.abs(lam_g - lam_o) <= 1e-4 * np.abs(lam_o)), (lam_g, lam_o)
+    print(f"max relative weight difference {np.max(np.abs(lam_g - lam_o) / np.abs(lam_o)):.3e}", flush=True)
+    assert np.all(np.abs(lam_g - lam_o) <= 1e-5 * np.abs(lam_o)), (lam_g, lam_o)
     agree = np.abs(np.sum(U_g * U_o, axis=1)) / np.linalg.norm(U_g, axis=1)
-    assert np.all(1.0 - agree <= 1e-4), agree
+    print(f"max 1 - |cos| {np.max(1.0 - agree):.3e}", flush=True)
+    assert np.all(1.0 - agree <= 1e-9), agree
     # and both found the planted basis in weight order
     assert list(np.abs(U_g @ A).argmax(axis=1)) == list(range(R))
 
@@ -60,8 +65,10 @@ def test_asymmetric_rtpm_matches_oracle(I, J, D, w, noise, L, iters):
     T = Tv.astype(np.float32).astype(np.float64).reshape((I, I, I), order="F")
     Y = np.stack([O.fcs_dense(T, hs[d], ss[d], (J, J, J)) for d in range(D)])
     lam_o, X_o = O.rtpm_asym(Y, hs, ss, (J, J, J), R, starts, iters)
-    assert np.all(np.abs(lam_g - lam_o) <= 1e-4 * np.abs(lam_o)), (lam_g, lam_o)
+    print(f"max relative weight difference {np.max(np.abs(lam_g - lam_o) / np.abs(lam_o)):.3e}", flush=True)
+    assert np.all(np.abs(lam_g - lam_o) <= 1e-5 * np.abs(lam_o)), (lam_g, lam_o)
     for n in range(3):
         agree = np.abs(np.sum(X_g[n] * X_o[n], axis=1)) / np.linalg.norm(X_g[n], axis=1)
-        assert np.all(1.0 - agree <= 1e-4), (n, agree)
+        print(f"mode {n}: max 1 - |cos| {np.max(1.0 - agree):.3e}", flush=True)
+        assert np.all(1.0 - agree <= 1e-9), (n, agree)
         assert list(np.abs(X_g[n] @ F[n]).argmax(axis=1)) == list(range(R))
