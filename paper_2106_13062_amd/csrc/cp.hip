@@ -530,8 +530,16 @@ static size_t factor_bin_bytes(const fcs_plan *p, int64_t pairs) {
     return align256((size_t)p->D * (size_t)pairs * (p->J[0] + p->J[1] - 1 + p->J[2] + p->J[3] - 1) * 8);
 }
 
+// A Kronecker sketch with many stored slices runs as the contraction of
+// shared length 1 (its slices spread over workgroups); otherwise one
+// workgroup per sketch does the whole of it.
+static bool kron_as_contraction(const fcs_plan *p) { return p->Qh > 2; }
+
+size_t fcs_ws_contraction(const fcs_plan *p, int64_t Lc);
+
 size_t fcs_ws_kron(const fcs_plan *p) {
     if (p->N != 4) return 256;
+    if (kron_as_contraction(p)) return fcs_ws_contraction(p, 1);
     return factor_float_bytes(p, 1) + factor_bin_bytes(p, 1);
 }
 
@@ -690,12 +698,14 @@ extern "C" fcs_status fcs_sketch_kron(fcs_plan_t p, const float *A, const float 
     if (p->P == 0) FCS_FAIL(FCS_EUNSUPPORTED, "no transform length fits this plan");
     if (!A || !B) FCS_FAIL(FCS_EINVAL, "null factor matrix");
     if (!out && !spec) FCS_FAIL(FCS_EINVAL, "neither out nor spec given");
-    CpDesc c{};
-    desc_from_plan(c, p);
-    c.kind = FCS_DESC_KRON;
     const size_t need = fcs_ws_kron(p);
     if (!ws || ws_bytes < need) FCS_FAIL(FCS_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, need);
     if (!fcs_aligned(ws, 16)) FCS_FAIL(FCS_EINVAL, "workspace not 16-byte aligned");
+    // A (x) B is the contraction of A (I_0 x I_1 x 1) with B (1 x I_2 x I_3)
+    if (kron_as_contraction(p)) return fcs_sketch_contraction(p, 1, A, B, out, spec, ws, ws_bytes, stream);
+    CpDesc c{};
+    desc_from_plan(c, p);
+    c.kind = FCS_DESC_KRON;
     c.U[0] = A;
     c.U[1] = B;
     c.R = 1;
