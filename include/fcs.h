@@ -276,9 +276,13 @@ FCS_API fcs_status fcs_sketch_cp_noalloc(fcs_plan_t plan, int64_t R, const float
  * largest magnitude of a matrix maps into [2^(B-1), 2^B) with
  * B = min(40, 62 - ceil(log2 of its entry count)), so rounding moves the
  * sketch by at most sqrt(entries) 2^-B of its norm), then transformed,
- * multiplied and inverted in float.
- *   plan  order-4 plan; (J_0 + J_1 - 1) and (J_2 + J_3 - 1) 64-bit bins must
- *         fit in LDS (about 20000 bins)
+ * multiplied and inverted in float.  Bins that do not fit in LDS (more than
+ * about 20000) are kept in the workspace; a matrix with at most four
+ * entries per bin on average is then summed with float atomics instead (a
+ * bin's few entries in an order that is not fixed).  A plan with more than
+ * two stored slices (Q > 4) computes the sketch as fcs_sketch_contraction
+ * with Lc = 1, whose tiles spread the slices over workgroups.
+ *   plan  order-4 plan
  *   A     device, float, I_0 x I_1 column-major (vec(A))
  *   B     device, float, I_2 x I_3 column-major
  *   out   device, float, D x J~; overwritten (may be NULL if spec is set)
@@ -316,9 +320,9 @@ FCS_API fcs_status fcs_contract_full(fcs_plan_t plan, const float *spec, int64_t
  * linearity it is the sum over l of the Kronecker-product sketches of the
  * slices A(:,:,l) and B(l,:,:); the spectra of the slice products are summed
  * over l before one inverse transform per slice.  Each slice's order-2
- * sketch is summed exactly in 64-bit fixed point as in fcs_sketch_kron.
+ * sketch is summed as in fcs_sketch_kron.
  *   plan  order-4 plan; modes 0, 1 index A's first two modes, 2, 3 B's last
- *         two; (J_0 + J_1 - 1) and (J_2 + J_3 - 1) 64-bit bins fit in LDS
+ *         two
  *   Lc    length of the shared index, 1 .. 2^20 (Lc = 1: the Kronecker
  *         product of A(:,:,0) and B(0,:,:))
  *   A     device, float, I_0 x I_1 x Lc column-major (mode 0 fastest)

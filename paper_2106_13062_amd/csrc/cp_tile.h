@@ -328,24 +328,37 @@ __device__ __forceinline__ void build_seq_slice(float2 (&wv)[Shape<P>::E], const
     constexpr int E = Shape<P>::E;
     const int t = tid_opaque();
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int m = t + e * T;
-        float2 acc = make_float2(0.f, 0.f);
-        int qt = 0;
-        for (int j = m; j < M; j += P) {
-            const float v = y[j];
-            if (q == 0) {
-                acc.x += v;
-            } else {
-                const float2 w = s.twL[qt * P];
-                acc.x += v * w.x;
-                acc.y += v * w.y;
-                qt += q;
-                if (qt >= s.Q) qt -= s.Q;
-            }
+    for (int e = 0; e < E; ++e) wv[e] = make_float2(0.f, 0.f);
+    // fold round k adds y[m + kP] for all E positions of the thread, so the
+    // E loads of a round are in flight together (the rounds are few:
+    // ceil(M / P)); the fold root exp(-2 pi i q k / Q) is the same for the
+    // whole workgroup
+    const int nfold = (M + P - 1) / P;
+    int qt = 0;
+    for (int k = 0; k < nfold; ++k) {
+        float v[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int j = t + e * T + k * P;
+            v[e] = j < M ? y[j] : 0.f;
         }
-        if (q != 0) acc = cmul(acc, s.twL[q * m]);
-        wv[e] = acc;
+        if (q == 0) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) wv[e].x += v[e];
+        } else {
+            const float2 w = s.twL[qt * P];
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                wv[e].x += v[e] * w.x;
+                wv[e].y += v[e] * w.y;
+            }
+            qt += q;
+            if (qt >= s.Q) qt -= s.Q;
+        }
+    }
+    if (q != 0) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) wv[e] = cmul(wv[e], s.twL[q * (t + e * T)]);
     }
 }
 
@@ -642,6 +655,32 @@ __device__ __forceinline__ void kron_factor_sketch(const float *__restrict__ M, 
     }
     if (M0 < 0.f) {
         for (int j = t; j < nb; j += T) y[j] = __builtin_nanf("");
+        return;
+    }
+    if (gbins && n <= 4 * (int64_t)nb) {
+        // bins in global memory and sparse (at most four entries per bin on
+        // average): float atomics straight into y, whose clearing and reading
+        // is then the only traffic besides the entries (the 64-bit bins would
+        // be cleared, added to and read back in full)
+        for (int j = t; j < nb; j += T) y[j] = 0.f;
+        __threadfence();
+        __syncthreads();
+        int i = t % Ia, j = t / Ia;
+        const int st_i = T % Ia, st_j = T / Ia;
+        for (int64_t k = t; k < n; k += T) {
+            const uint32_t wa = ta[i], wb = tb[j];
+            const int bin = (int)(wa & FCS_H_MASK) + (int)(wb & FCS_H_MASK);
+            const float v = M[STRIDED ? k * stride : k];
+            unsafeAtomicAdd(&y[bin], ((wa ^ wb) & FCS_S_BIT) ? -v : v);
+            i += st_i;
+            j += st_j;
+            if (i >= Ia) {
+                i -= Ia;
+                ++j;
+            }
+        }
+        __threadfence();
+        __syncthreads();
         return;
     }
     const int lgn = n > 1 ? 64 - __clzll((unsigned long long)(n - 1)) : 0;
