@@ -91,6 +91,25 @@ def test_kron_long_hashes_sum_factor_bins_in_global_memory(J):
         assert rel(y[d], want) <= TOL, (d, rel(y[d], want))
 
 
+def test_kron_dense_factors_with_global_64bit_bins():
+    """Factor matrices with more than four entries per factor-sketch bin
+    (400 x 400 and 300 x 300 into J_0 + J_1 - 1 = 29999 bins, too many for
+    LDS): the bins stay 64-bit fixed point, in global memory, and the sketch
+    (three stored slices, so computed as a one-slice contraction) matches
+    the oracle."""
+    I, J, D, seed = (400, 400, 300, 300), (15000,) * 4, 2, 29
+    A = synth.uniform_matrix(22, (400, 400), stream=1)
+    B = synth.uniform_matrix(22, (300, 300), stream=2)
+    plan = Plan(I, J, D, seed, device=DEV)
+    y, _ = plan.sketch_kron(colmajor(A), colmajor(B))
+    y = y.cpu().numpy()
+    hs, ss = O.hash_tables(seed, D, I, J)
+    for d in range(D):
+        want = O.kron_fcs(A.astype(np.float32).astype(np.float64), B.astype(np.float32).astype(np.float64),
+                          hs[d], ss[d], J)
+        assert rel(y[d], want) <= TOL, (d, rel(y[d], want))
+
+
 def _instances(count, seed, kron_every=5, I_range=(8, 400), R_range=(1, 40), logJ_range=(5, 11)):
     return synth.batch_instances(count, seed=seed, hash_seed=seed + 7, kron_every=kron_every,
                                  I_range=I_range, R_range=R_range, logJ_range=logJ_range)

@@ -45,6 +45,13 @@ CP_CASES = [
     ((12, 11, 10, 9, 8), (16, 16, 16, 16, 16), 4, 2, 0),
     ((2000, 1500, 700), (1024, 2048, 512), 33, 4, 0),   # folding (J_n > P) and several slices
     ((300, 300, 300), (5000, 5000, 5000), 3, 2, 0),
+    # Q = 2: both stored slices are conjugate-symmetric, so both pack modes
+    # (0, 1) and (2, 3) into shared transforms
+    ((60, 50, 40, 30), (100, 90, 80, 70), 5, 2, 32768),
+    # Q = 4: slices 0 and 2 pack modes (0, 1) with mode 2 alone, slice 1 does not pack
+    ((60, 50, 40), (100, 90, 80), 4, 3, 65536),
+    # order 5 on Q = 2: pairs (0, 1), (2, 3) and mode 4 alone
+    ((12, 11, 10, 9, 8), (16, 16, 16, 16, 16), 3, 2, 32768),
 ]
 
 
