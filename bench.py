@@ -913,6 +913,13 @@ def serve_workload(args, torch, dev):
         # saturated: completions fall clearly behind the arrivals
         row["saturated"] = bool(row["served_req_s"] < 0.9 * row["arrival_req_s"])
         row["plain_saturated"] = bool(plain_rate < 0.9 * row["arrival_req_s"])
+    # the highest offered rate the loop keeps up with, and its latencies
+    ok = [row for row in out["rates"] if not row["saturated"]]
+    if ok:
+        top = max(ok, key=lambda x: x["offered_req_s"])
+        out["highest_unsaturated"] = {"offered_req_s": top["offered_req_s"], "served_req_s": top["served_req_s"],
+                                      "p50_ms": top["p50_ms"], "p99_ms": top["p99_ms"],
+                                      "vs_plain_capacity": top["served_req_s"] / out["plain"]["req_s"]}
     # alone-versus-mix parity on a sample of a mixed run
     reqs = serve_requests(srv, args, rates[len(rates) // 2], 600, 4242)
     srv.run(reqs, timeout=120)
@@ -1094,7 +1101,8 @@ def main():
     ap.add_argument("--batch-count", type=int, default=4096, help="instances of the uneven batch")
     ap.add_argument("--batch-reps", type=int, default=3, help="timed passes of each batch path")
     ap.add_argument("--no-tune", dest="tune", action="store_false", help="skip the batch autotuner")
-    ap.add_argument("--serve-rates", default="2000,5000,10000,20000,50000", help="offered request rates (1/s)")
+    ap.add_argument("--serve-rates", default="2000,5000,10000,20000,30000,40000,50000",
+                    help="offered request rates (1/s)")
     ap.add_argument("--serve-seconds", type=float, default=0.5, help="arrival span per rate")
     ap.add_argument("--serve-max", type=int, default=25000, help="most requests per rate")
     ap.add_argument("--serve-pairs", type=int, default=1024, help="(u, v) pairs in the bank")

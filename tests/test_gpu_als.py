@@ -17,11 +17,14 @@ pytestmark = pytest.mark.gpu
 DEV = torch.device("cuda:0")
 
 
-@pytest.mark.parametrize("I,J,D,w,noise,iters,tseed,hseed,iseed", [
-    (16, 4096, 3, (3.0, 2.0, 1.0), 0.0, 15, 12, 22, 32),
-    (20, 4096, 3, (2.0, 1.0), 0.01, 12, 13, 23, 33),
+@pytest.mark.parametrize("I,J,D,w,noise,iters,tseed,hseed,iseed,rec", [
+    (16, 4096, 3, (3.0, 2.0, 1.0), 0.0, 15, 12, 22, 32, 0.99),
+    (20, 4096, 3, (2.0, 1.0), 0.01, 12, 13, 23, 33, 0.99),
+    # J_n = 5000, D = 10 as in the paper: the sketch's own error at I_n = 100
+    # limits recovery to about 0.98 (the oracle's as well)
+    (100, 5000, 10, (3.0, 2.0, 1.0), 0.0, 10, 14, 24, 34, 0.97),
 ])
-def test_als_matches_oracle(I, J, D, w, noise, iters, tseed, hseed, iseed):
+def test_als_matches_oracle(I, J, D, w, noise, iters, tseed, hseed, iseed, rec):
     print(f"als I={I} J={J} D={D} R={len(w)}", flush=True)
     R = len(w)
     Tv, F = synth.asymmetric_cp_tensor(tseed, I, w, noise)
@@ -42,7 +45,7 @@ def test_als_matches_oracle(I, J, D, w, noise, iters, tseed, hseed, iseed):
         cos = np.abs(np.sum(G_g[n] * G_o[n], axis=0)) / np.linalg.norm(G_g[n], axis=0)
         print(f"mode {n}: max 1 - |cos| {np.max(1.0 - cos):.3e}", flush=True)
         assert np.all(1.0 - cos <= 1e-9), (n, cos)
-        assert np.all(np.abs(G_g[n].T @ F[n]).max(axis=1) >= 0.99)
+        assert np.all(np.abs(G_g[n].T @ F[n]).max(axis=1) >= rec)
 
 
 def test_als_rejects_bad_shapes():

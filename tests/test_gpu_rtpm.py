@@ -21,6 +21,7 @@ DEV = torch.device("cuda:0")
 @pytest.mark.parametrize("I,J,D,w,noise,L,iters", [
     (20, 2048, 3, (3.0, 2.0, 1.0), 0.0, 5, 12),
     (32, 1024, 2, (4.0, 3.0, 2.0, 1.0), 0.01, 4, 10),
+    (100, 5000, 2, (3.0, 2.0, 1.0), 0.0003, 5, 10),     # the paper's I_n = 100, J_n = 5000, D = 2
 ])
 def test_rtpm_matches_oracle(I, J, D, w, noise, L, iters):
     R = len(w)

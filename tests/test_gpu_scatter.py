@@ -221,11 +221,15 @@ def test_coo_equals_dense_of_same_entries():
 
 
 def test_coo_full_size_workload():
-    """10 % Bernoulli mask of a 1024 x 1024 x 256 slice (quarter of the
-    1024^3 workload, same density and index structure), int32 coordinates."""
+    """The 10 % COO workload at full size: a Bernoulli(0.1) mask of the
+    1024^3 tensor (1.07e8 nonzeros, int32 coordinates), J_n = 4096, D = 8,
+    in the launch configuration the benchmark times; every sketch against
+    the FP64 oracle."""
     cfg = synth.DENSE1024
-    I = (1024, 1024, 256)
+    I = cfg.I
+    print("coo full size: generating the entries", flush=True)
     T, idx, val = _coo(I, cfg.density, cfg.data_seed)
+    del T
     plan = Plan(I, cfg.J, cfg.D, cfg.hash_seed, device=DEV)
     got = plan.sketch_coo(dev(idx), dev(val)).cpu().numpy()
     hs, ss = O.hash_tables(cfg.hash_seed, cfg.D, I, cfg.J)
