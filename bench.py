@@ -935,6 +935,25 @@ def serve_workload(args, torch, dev):
     return out
 
 
+def copy_ceiling_gbs(torch, dev, nbytes=1 << 30, reps=10):
+    """Measured HBM ceiling: a plain device-to-device copy of nbytes (read
+    once, written once), timed with HIP events, in GB/s of bytes moved."""
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device=dev).uniform_()
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9
+
+
 def copy_calibration(torch, dev, nbytes=1 << 30, reps=5):
     """A plain device-to-device copy of known size, for scaling the
     FETCH_SIZE / WRITE_SIZE counters of the profiled kernels."""
@@ -1156,6 +1175,7 @@ def main():
               flush=True)
         return
     cfg, res, cpu, T = dense_workload(args, torch, dev)
+    copy_gbs = copy_ceiling_gbs(torch, dev)
     secondary = {}
     if args.mode == "full":
         import synth
@@ -1215,7 +1235,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": res["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": res["achieved_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "dense_scatter_kernel", "launch_ms": res["event_ms"],
-                     "alg_bytes_per_launch": res["alg_bytes"]},
+                     "alg_bytes_per_launch": res["alg_bytes"],
+                     "copy_ceiling": copy_gbs, "frac_of_copy_ceiling": res["achieved_gbs"] / copy_gbs},
         "cpu_baseline": cpu,
         "secondary": secondary,
     }
