@@ -578,7 +578,7 @@ static fcs_status cp_check_args(const fcs_plan *p, int64_t R, const float *const
     if (!p || !p->bound) FCS_FAIL(FCS_EINVAL, "plan is null or not bound");
     if (p->P == 0) FCS_FAIL(FCS_EUNSUPPORTED, "no transform length fits this plan");
     if (R < 0) FCS_FAIL(FCS_EINVAL, "R < 0");
-    if (R > INT32_MAX) FCS_FAIL(FCS_EUNSUPPORTED, "R too large");
+    if (R > INT32_MAX / FCS_MAX_ORDER) FCS_FAIL(FCS_EUNSUPPORTED, "R too large");
     if (!out && !spec) FCS_FAIL(FCS_EINVAL, "neither out nor spec given");
     if (R > 0 && !U) FCS_FAIL(FCS_EINVAL, "null factor array");
     for (int n = 0; n < p->N; ++n)
@@ -785,7 +785,7 @@ extern "C" fcs_status fcs_contract_free_mode(fcs_plan_t p, const float *spec, in
     if (Pn == 0) return FCS_OK;
     for (int n = 0; n < p->N; ++n)
         if (p->I[n] >= FCS_MAX_GATHER_INDEX) FCS_FAIL(FCS_EUNSUPPORTED, "contractions need I_n < 2^30");
-    if (Pn > INT32_MAX / std::max<int>(1, p->D)) FCS_FAIL(FCS_EUNSUPPORTED, "too many vector tuples");
+    if (Pn > INT32_MAX / std::max<int>(FCS_MAX_ORDER, p->D)) FCS_FAIL(FCS_EUNSUPPORTED, "too many vector tuples");
     if (!spec || !out || !vecs) FCS_FAIL(FCS_EINVAL, "null spectrum, output or vector array");
     for (int n = 0; n < p->N; ++n)
         if (n != free_mode && !vecs[n]) FCS_FAIL(FCS_EINVAL, "null vector block %d", n);
