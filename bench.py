@@ -230,7 +230,7 @@ def cp_workload(args, torch, dev, cfg, pairs=0, inner=False):
     if not args.no_cpu_baseline and cfg.R >= 64:
         import oracle as O
         hs, ss = O.hash_tables(cfg.hash_seed, cfg.D, cfg.I, cfg.J)
-        rs = 8                                  # ranks per sample job
+        rs = 32                                 # ranks per sample job (about 1 s of wall time)
         _POOL.update(U=U, hs=hs, ss=ss, J=cfg.J, L=Lp2)
         _, dt, procs = _pool_map(_cp_one, [(d, 0, rs) for d in range(cfg.D)], host_cores())
         _POOL.clear()
