@@ -96,6 +96,26 @@ def test_cp_sketch_wide_range_columns():
         assert rel(y[d], want) <= TOL, (d, rel(y[d], want))
 
 
+@pytest.mark.parametrize("L", [0, 32768])
+def test_cp_sketch_zero_columns_and_signed_weights(L):
+    """All-zero factor columns (a zero maximum and norm: scale exponent 0,
+    in a packed pair and alone) and weights of both signs, at the planner's
+    transform length and at Q = 2 (both slices pack)."""
+    I, J, R, D, seed = (70, 60, 50), (128, 96, 64), 6, 3, 17
+    U = synth.cp_factors(15, I, R)
+    U[0][:, 1] = 0.0
+    U[1][:, 2] = 0.0
+    U[2][:, 4] = 0.0
+    lam = np.array([1.5, -2.0, 0.5, -0.25, 3.0, -1.0], dtype=np.float32)
+    plan = Plan(I, J, D, seed, L=L, device=DEV)
+    y, _ = plan.sketch_cp(dev_factors(U), lam=dev(lam))
+    y = y.cpu().numpy()
+    hs, ss = O.hash_tables(seed, D, I, J)
+    for d in range(D):
+        want = O.fcs_cp_conv(lam, U, hs[d], ss[d], J)
+        assert rel(y[d], want) <= TOL, (d, rel(y[d], want))
+
+
 def test_cp_sketch_non_finite_column():
     """A NaN in one factor column makes every entry of every sketch NaN (the
     FFT spreads it over all bins), as a float sum does; the other sketches of
