@@ -39,10 +39,14 @@ namespace {
 template <int P>
 __global__ __launch_bounds__(Shape<P>::T) void cp_forward_kernel(CpDesc c) {
     extern __shared__ float2 lds[];
+    // tiles of the slices that pack two modes per transform (q = 0 and,
+    // Q even, q = Q/2) cost less: the others are dispatched first
     const int tile = blockIdx.x;
     const int chunk = tile % c.nchunks;
-    const int q = (tile / c.nchunks) % c.s.Qh;
-    const int d = tile / (c.nchunks * c.s.Qh);
+    const int d = (tile / c.nchunks) % c.D;
+    const int qi = tile / (c.nchunks * c.D);
+    const int nfull = c.s.Qh - 1 - ((c.s.Q % 2 == 0 && c.s.Q > 1) ? 1 : 0);
+    const int q = qi < nfull ? qi + 1 : (qi == nfull ? 0 : c.s.Q / 2);
     float2 acc[Shape<P>::E];
     cp_tile<P>(c, d, q, chunk, lds, acc);
     if (c.nchunks == 1)
