@@ -378,8 +378,20 @@ extern "C" fcs_status fcs_batch_create(const fcs_batch_item *items, int64_t coun
                 umax = 2 * (size_t)p->N * it.R * sizeof(float);
                 c.rchunk = (int)std::min<int64_t>(it.R, std::max<int64_t>(1, fcs_ceil_div(tile_ffts, p->N)));
                 c.nchunks = (int)fcs_ceil_div(it.R, c.rchunk);
-                double per_rank = 0.0;
-                for (int n = 0; n < p->N; ++n) per_rank += p->P * lg + 4.0 * std::max<int64_t>(p->I[n], p->P);
+                // per rank and mode: the count sketch (entries and bins)
+                // and one transform, except on the conjugate-symmetric
+                // slices, where two modes share a transform
+                double scat = 0.0;
+                int folded = 0;
+                for (int n = 0; n < p->N; ++n) {
+                    scat += 4.0 * std::max<int64_t>(p->I[n], p->P);
+                    folded += p->J[n] > p->P;
+                }
+                auto per_rank = [&](int q) {
+                    const bool packs = folded == 0 && (q == 0 || 2 * q == p->Q);
+                    const int ffts = packs ? (p->N + 1) / 2 : p->N;
+                    return scat + ffts * p->P * lg;
+                };
                 if (c.nchunks > 1) {
                     c.cnt_slice = b->nctr;
                     b->nctr += p->D * p->Qh;
@@ -395,7 +407,7 @@ extern "C" fcs_status fcs_batch_create(const fcs_batch_item *items, int64_t coun
                         for (int ch = 0; ch < c.nchunks; ++ch) {
                             const int nr = std::min(c.R, (ch + 1) * c.rchunk) - ch * c.rchunk;
                             b->cls[ci].tiles.push_back({(int32_t)i, d, q, ch});
-                            cost[ci].push_back(nr * per_rank);
+                            cost[ci].push_back(nr * per_rank(q));
                         }
             }
         } else {
