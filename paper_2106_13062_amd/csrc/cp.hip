@@ -13,10 +13,12 @@
 // (Q even) q = Q/2, else 2.  Any L >= J~ gives the linear convolution of the
 // paper's J~-point zero-padded transforms, truncated to J~.
 //
-// Count sketches inside the transforms are gathers, not scatters: the plan
-// holds the inverse hash lists (indices grouped by h_n), so the thread that
-// owns position m of a slice sums the entries of the buckets that fold onto
-// m.  No LDS atomics are needed (float LDS atomics are slow on gfx950).
+// Count sketches inside the transforms are scattered into LDS bins as 64-bit
+// fixed point scaled to each column's maximum (a small pre-kernel computes
+// the maxima; integer LDS atomics, since float LDS atomics are slow on
+// gfx950).  Hash lengths J_n > P fold several buckets onto one position
+// with complex weights; those sketches are gathered over the plan's inverse
+// hash lists (indices grouped by h_n) by the thread that owns the position.
 #include "fcs_internal.h"
 
 #include <algorithm>

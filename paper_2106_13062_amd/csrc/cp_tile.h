@@ -1,8 +1,12 @@
 // Device building blocks of the CP sketch (Section 3.1 of the paper) shared
 // by the single-plan kernels and the persistent batch kernels:
-//   - count sketches of factor columns built as gathers over the inverse
-//     hash lists, one interleaved slice of the L-point transform at a time
-//     (L = Q * P, P a power of two held in LDS; see cp.hip for the layout),
+//   - count sketches of factor columns, one interleaved slice of the
+//     L-point transform at a time (L = Q * P, P a power of two held in LDS;
+//     see cp.hip for the layout): scattered into 64-bit fixed-point LDS bins
+//     when J_n <= P, gathered over the inverse hash lists when J_n > P (the
+//     buckets fold onto P positions),
+//   - on the conjugate-symmetric slices, two modes packed into one complex
+//     transform and split through one LDS exchange,
 //   - one CP work tile: for a rank range, N mode spectra of one slice formed
 //     in LDS, multiplied in registers and summed,
 //   - the inverse: slice partial spectra summed, inverted and accumulated
