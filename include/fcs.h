@@ -443,6 +443,10 @@ typedef struct {
     int32_t wg_per_cu[7];     /* persistent workgroups per compute unit for the
                                  FFT sizes 2^8 .. 2^14; 0 = as many as LDS allows
                                  (at most 8)                                    */
+    int32_t no_pack[7];       /* per FFT size class: nonzero = one transform per
+                                 mode on every slice; 0 = two modes share one
+                                 transform on the conjugate-symmetric slices
+                                 (q = 0 and, Q even, Q/2), as fcs_sketch_cp    */
 } fcs_batch_config;
 
 typedef struct fcs_batch *fcs_batch_t;

@@ -35,7 +35,7 @@ class BatchItem(ctypes.Structure):
 
 
 class BatchConfig(ctypes.Structure):
-    _fields_ = [("tile_ffts", I32), ("wg_per_cu", I32 * 7)]
+    _fields_ = [("tile_ffts", I32), ("wg_per_cu", I32 * 7), ("no_pack", I32 * 7)]
 
 
 # (name, restype, argtypes); every entry point of include/fcs.h

@@ -1,19 +1,22 @@
 """Measured tuning of the batched sketch launch (include/fcs.h, fcs_batch_*).
 
-The batch has three free parameters that the work itself does not fix: the
+The batch has four free parameters that the work itself does not fix: the
 transform split L = Q * P of every CP item (``tune_lengths``: the weight of
-a count-sketch gather against an FFT point in the length model; fewer,
-longer transforms repeat fewer gathers), how many forward FFTs a CP work
-tile holds (``tile_ffts``: small tiles balance the queue, large ones write
-fewer partial spectra) and how many persistent workgroups each FFT size
+a count-sketch pass against an FFT point in the length model; fewer,
+longer transforms repeat fewer count sketches), how many forward FFTs a CP
+work tile holds (``tile_ffts``: small tiles balance the queue, large ones
+write fewer partial spectra), how many persistent workgroups each FFT size
 class keeps per compute unit (``wg_per_cu``: more hide latency, fewer leave
-LDS and registers to each).
+LDS and registers to each) and, per class, the transform structure of the
+conjugate-symmetric slices (``no_pack``: two modes packed into one complex
+transform and split by one LDS exchange, or one transform per mode).
 
 ``tune_batch`` times candidate configurations on the real batch (graph
 replays, HIP events on the launch stream) by coordinate descent: first
-``tile_ffts``, then the workgroups per CU of each populated class, keeping a
-candidate only when it is faster.  Results can be cached in a JSON file keyed
-by a signature of the batch shape.
+``tile_ffts``, then the workgroups per CU of each populated class, then the
+packing of each populated class, keeping a candidate only when it is faster.
+Results can be cached in a JSON file keyed by a signature of the batch
+shape.
 """
 from __future__ import annotations
 
@@ -136,12 +139,12 @@ def tune_batch(items, runs: int = 3, warmup: int = 1, cache: str | None = None, 
             log(f"autotune {cfg} -> {ms:.3f} ms")
         return ms, grids
 
-    best = {"tile_ffts": 32, "wg_per_cu": [0] * NCLASS}
+    best = {"tile_ffts": 32, "wg_per_cu": [0] * NCLASS, "no_pack": [0] * NCLASS}
     best_ms, grids = run(best)
     for tf in TILE_FFTS:
         if tf == best["tile_ffts"]:
             continue
-        cfg = {"tile_ffts": tf, "wg_per_cu": list(best["wg_per_cu"])}
+        cfg = {"tile_ffts": tf, "wg_per_cu": list(best["wg_per_cu"]), "no_pack": list(best["no_pack"])}
         ms, _ = run(cfg)
         if ms < best_ms:
             best, best_ms = cfg, ms
@@ -149,13 +152,23 @@ def tune_batch(items, runs: int = 3, warmup: int = 1, cache: str | None = None, 
     present = [c for c in range(NCLASS) if grids[c] > 0]
     for c in present:
         for w in WPC:
-            cfg = {"tile_ffts": best["tile_ffts"], "wg_per_cu": list(best["wg_per_cu"])}
+            cfg = {"tile_ffts": best["tile_ffts"], "wg_per_cu": list(best["wg_per_cu"]),
+                   "no_pack": list(best["no_pack"])}
             cfg["wg_per_cu"][c] = w
             if cfg == best:
                 continue
             ms, _ = run(cfg)
             if ms < best_ms:
                 best, best_ms = cfg, ms
+    # transform structure per class: two modes per transform on the
+    # conjugate-symmetric slices (fewer transforms, one more LDS exchange and
+    # more live registers) or one transform per mode
+    for c in present:
+        cfg = {"tile_ffts": best["tile_ffts"], "wg_per_cu": list(best["wg_per_cu"]), "no_pack": list(best["no_pack"])}
+        cfg["no_pack"][c] = 1 - cfg["no_pack"][c]
+        ms, _ = run(cfg)
+        if ms < best_ms:
+            best, best_ms = cfg, ms
     if cache:
         known = {}
         if os.path.exists(cache):

@@ -217,6 +217,8 @@ struct fcs_batch {
         int grid = 0;
     };
     std::vector<CpDesc> desc;            // device pointers patched at prepare
+    std::vector<int> cls_of;             // FFT size class of every item
+    bool no_pack[NCLASS] = {};           // classes without two-mode packing
     std::vector<size_t> part_off, ytmp_off, kscr_off, umax_off;
     std::vector<AbsmaxEntry> absmax;     // column-max work, out_off patched at create
     size_t absmax_off = 0, umax_base = 0;
@@ -317,6 +319,7 @@ extern "C" fcs_status fcs_batch_create(const fcs_batch_item *items, int64_t coun
     if (count > INT32_MAX / FCS_MAX_D) FCS_FAIL(FCS_EUNSUPPORTED, "too many items");
     const int tile_ffts = (cfg && cfg->tile_ffts > 0) ? cfg->tile_ffts : 32;
     fcs_batch *b = new fcs_batch();
+    for (int ci = 0; ci < NCLASS; ++ci) b->no_pack[ci] = cfg && cfg->no_pack[ci] != 0;
     std::vector<std::vector<double>> cost(NCLASS);
     for (int64_t i = 0; i < count; ++i) {
         const fcs_batch_item &it = items[i];
@@ -416,6 +419,7 @@ extern "C" fcs_status fcs_batch_create(const fcs_batch_item *items, int64_t coun
         b->cls[ci].P = (int)p->P;
         b->cls[ci].lds = std::max(b->cls[ci].lds, cp_lds_bytes((int)p->P, c));
         b->desc.push_back(c);
+        b->cls_of.push_back(ci);
         b->part_off.push_back(part);
         b->ytmp_off.push_back(ytmp);
         b->kscr_off.push_back(kscr);
@@ -497,7 +501,10 @@ extern "C" fcs_status fcs_batch_prepare(fcs_batch_t b, void *ws, size_t ws_bytes
         b->desc[i].ytmp = b->ytmp_off[i] ? reinterpret_cast<float *>(w + b->ytmp_off[i]) : nullptr;
         b->desc[i].kscratch = b->kscr_off[i] ? reinterpret_cast<float *>(w + b->kscr_off[i]) : nullptr;
         b->desc[i].umax = b->umax_off[i] ? reinterpret_cast<const float *>(w + b->umax_off[i]) : nullptr;
-        b->desc[i].uexp = b->desc[i].umax ? b->desc[i].umax + (int64_t)b->desc[i].N * b->desc[i].R : nullptr;
+        // without the norm exponents the tiles transform every mode alone
+        b->desc[i].uexp = (b->desc[i].umax && !b->no_pack[b->cls_of[i]])
+                              ? b->desc[i].umax + (int64_t)b->desc[i].N * b->desc[i].R
+                              : nullptr;
     }
     if (!b->absmax.empty())
         FCS_HIP_CHECK(hipMemcpyAsync(w + b->absmax_off, b->absmax.data(), b->absmax.size() * sizeof(AbsmaxEntry),

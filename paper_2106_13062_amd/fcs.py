@@ -330,7 +330,8 @@ class Batch:
       lam    optional float32 R weights (CP)
       out    float32 (D, J~) output tensor (allocated when missing)
       spec   optional float32 (D, spec_len, 2) spectrum output
-    config: optional dict with "tile_ffts" and "wg_per_cu" (7 ints)."""
+    config: optional dict with "tile_ffts", "wg_per_cu" (7 ints) and
+    "no_pack" (7 flags: one transform per mode in that FFT size class)."""
 
     def __init__(self, items, config=None, device=None):
         self.lib = C.load()
@@ -376,7 +377,8 @@ class Batch:
         cfg = None
         if config:
             cfg = C.BatchConfig(int(config.get("tile_ffts", 0)),
-                                (ctypes.c_int32 * 7)(*[int(x) for x in config.get("wg_per_cu", [0] * 7)]))
+                                (ctypes.c_int32 * 7)(*[int(x) for x in config.get("wg_per_cu", [0] * 7)]),
+                                (ctypes.c_int32 * 7)(*[int(x) for x in config.get("no_pack", [0] * 7)]))
         h = ctypes.c_void_p()
         C.check(self.lib.fcs_batch_create(arr, n, None if cfg is None else ctypes.byref(cfg), ctypes.byref(h)))
         self._h = h

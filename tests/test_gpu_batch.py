@@ -154,7 +154,8 @@ def _oracle(plan, host, d):
     return O.fcs_cp_fft(lam, F, hs[d], ss[d], plan.J, plan.L)
 
 
-@pytest.mark.parametrize("D,cfg", [(1, None), (3, {"tile_ffts": 4}), (2, {"tile_ffts": 200, "wg_per_cu": [1] * 7})])
+@pytest.mark.parametrize("D,cfg", [(1, None), (3, {"tile_ffts": 4}), (2, {"tile_ffts": 200, "wg_per_cu": [1] * 7}),
+                                   (2, {"no_pack": [1, 0, 1, 0, 1, 0, 1]})])
 def test_batch_equals_alone_and_oracle(D, cfg):
     insts = _instances(40, seed=900 + D)
     items, plans, host = _make_items(insts, D=D, kron_I=(40, 30, 20, 50))
