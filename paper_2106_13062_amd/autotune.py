@@ -34,13 +34,16 @@ WPC = (1, 2, 4, 8)
 NCLASS = 7
 
 
-def choose_length(I, J, gather_weight: float = 4.0, min_fft: int = 256, max_fft: int = 16384) -> int:
+def choose_length(I, J, gather_weight: float = 16.0, min_fft: int = 256, max_fft: int = 16384) -> int:
     """Transform length L = Q * P for a CP sketch, by the planner's cost
-    model with a given weight of a count-sketch gather (per bucket or entry)
-    relative to one FFT point-stage: per stored slice, sum_n
-    (w (J_n + I_n) + P log2 P) plus the inverse P log2 P.  A larger weight
-    favours fewer, longer FFTs."""
+    model with a given weight of a count sketch (per bucket or entry)
+    relative to one FFT point-stage: per stored slice, sum_n w (J_n + I_n)
+    plus the inverse P log2 P, and P log2 P per forward transform, of which
+    the conjugate-symmetric slices (q = 0 and, Q even, Q/2) need one per
+    pair of modes when no hash is folded (J_n <= P).  A larger weight
+    favours fewer, longer FFTs.  The library planner uses w = 16."""
     Jt = sum(J) - len(J) + 1
+    N = len(J)
     best, best_L = None, 0
     P = min_fft
     while P <= max_fft:
@@ -48,7 +51,11 @@ def choose_length(I, J, gather_weight: float = 4.0, min_fft: int = 256, max_fft:
         if Q <= 64:
             Qh = Q // 2 + 1
             fft = P * math.log2(P)
-            cost = Qh * (sum(gather_weight * (j + i) + fft for i, j in zip(I, J)) + fft)
+            folded = any(j > P for j in J)
+            nself = 2 if (Q % 2 == 0 and Q > 1) else 1
+            packed = N if folded else (N + 1) // 2
+            cost = (Qh * (sum(gather_weight * (j + i) for i, j in zip(I, J)) + fft)
+                    + fft * (nself * packed + (Qh - nself) * N))
             if best is None or cost < best:
                 best, best_L = cost, P * Q
         P *= 2
@@ -104,7 +111,7 @@ def _trial(items, cfg, runs, warmup, device):
     return ms, grids
 
 
-def tune_lengths(build_items, weights=(1.0, 4.0, 16.0), runs: int = 2, warmup: int = 1, device=None, log=None):
+def tune_lengths(build_items, weights=(4.0, 16.0, 64.0), runs: int = 2, warmup: int = 1, device=None, log=None):
     """Pick the gather weight of the transform-length model by timing the
     batch built with each candidate (``build_items(weight)`` returns the
     items with plans made for that weight); returns (weight, items, table)."""

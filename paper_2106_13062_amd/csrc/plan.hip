@@ -137,16 +137,24 @@ fcs_status fcs_zero_fill(float *p, int64_t n, hipStream_t s) {
 // transform length: L = Q * P, P a power of two in [FCS_MIN_FFT, FCS_MAX_FFT]
 // ---------------------------------------------------------------------------
 static double cp_cost(const fcs_plan *p, int64_t P, int Q) {
-    // per (sketch, rank) and stored slice: for each mode a count-sketch
-    // gather over its J_n buckets and I_n entries (about four memory
-    // operations per bucket or entry) and one P-point FFT (about one unit per
-    // point and radix-2 stage); plus the inverse of the slice
+    // per (sketch, rank) and stored slice: for each mode a count sketch over
+    // its I_n entries and J_n buckets (weight 16 per entry or bucket against
+    // one FFT point and radix-2 stage: the measured optimum of the batch
+    // autotuner's length model) and one P-point FFT, except on the
+    // conjugate-symmetric slices (q = 0 and, Q even, Q/2), where two modes
+    // share a transform when no hash is folded; plus the inverse of the slice
     const int Qh = Q / 2 + 1;
     const double lg = std::log2((double)P);
     const double fft = (double)P * lg;
-    double per_mode = 0.0;
-    for (int n = 0; n < p->N; ++n) per_mode += 4.0 * (double)(p->J[n] + p->I[n]) + fft;
-    return (double)Qh * (per_mode + fft);
+    double sketch = 0.0;
+    bool folded = false;
+    for (int n = 0; n < p->N; ++n) {
+        sketch += 16.0 * (double)(p->J[n] + p->I[n]);
+        folded = folded || p->J[n] > P;
+    }
+    const int nself = (Q % 2 == 0 && Q > 1) ? 2 : 1;
+    const int packed = folded ? p->N : (p->N + 1) / 2;
+    return (double)Qh * (sketch + fft) + fft * ((double)nself * packed + (double)(Qh - nself) * p->N);
 }
 
 static bool choose_transform(fcs_plan *p, int64_t Lreq) {
