@@ -44,7 +44,26 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
     tmp = LIB + ".tmp%d" % os.getpid()
     subprocess.check_call([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs])
     os.replace(tmp, LIB)
+    build_examples(verbose)
     return LIB
+
+
+EXAMPLES = os.path.join(HERE, "examples")
+ROCM = os.path.dirname(os.path.dirname(os.path.realpath(HIPCC)))
+
+
+def build_examples(verbose: bool = False) -> None:
+    """Plain C programs that use only include/fcs.h, libfcs.so and the HIP
+    runtime (gcc, no hipcc): the library's C ABI without Python."""
+    for src in sorted(glob.glob(os.path.join(EXAMPLES, "*.c"))):
+        exe = src[:-2]
+        cmd = ["gcc", "-O2", "-std=c99", "-Wall", "-D__HIP_PLATFORM_AMD__",
+               "-I" + os.path.join(ROCM, "include"), "-I" + os.path.join(ROOT, "include"), src,
+               "-L" + HERE, "-lfcs", "-L" + os.path.join(ROCM, "lib"), "-lamdhip64",
+               "-Wl,-rpath,$ORIGIN/..", "-Wl,-rpath," + os.path.join(ROCM, "lib"), "-o", exe]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.check_call(cmd)
 
 
 def _wait(procs):
