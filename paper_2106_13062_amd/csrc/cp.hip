@@ -242,6 +242,8 @@ struct FreeArgs {
     float *est;             // [Pn][I_f][D]
     const float *umax;      // free mode: max_i |v_n(i)| of tuple p at [n * Pn + p] (fixed-point
                             // scatter of the count sketches), or null (gather)
+    const float *uexp;      // free mode: norm exponents of the same vectors (two modes packed per
+                            // transform on the conjugate-symmetric slices), or null
     double *full;           // full contraction: [Pn][D]
 };
 
@@ -261,11 +263,30 @@ __global__ __launch_bounds__(Shape<P>::T) void free_mode_kernel(FreeArgs a) {
         const float2 *sp = a.spec + ((int64_t)d * a.s.Qh + q) * P;
 #pragma unroll
         for (int e = 0; e < E; ++e) X[e] = sp[threadIdx.x + e * T];
+        const bool selfconj = (q == 0) || (2 * q == a.s.Q);
         for (int n = 0; n < a.N; ++n) {
             if (n == f) continue;
             const int32_t *off = invd + a.ioff[n];
             const float *vn = a.vecs[n] + (int64_t)p * a.I[n];
             float2 F[E];
+            const int nb = (n + 1 == f) ? n + 2 : n + 1;     // the next mode with a vector
+            if (selfconj && a.uexp && nb < a.N && a.J[n] <= P && a.J[nb] <= P) {
+                // two vectors' count sketches share one transform (as in the
+                // CP tiles), each scaled to a norm in [1/2, 1)
+                const int ea = (int)a.uexp[(int64_t)n * a.Pn + p];
+                const int eb = (int)a.uexp[(int64_t)nb * a.Pn + p];
+                scatter_cs_slice<P>(F, lds, vn, a.tab + (int64_t)d * a.sumI + a.off[n], a.I[n], a.J[n], q, a.s,
+                                    ldexpf(1.0f, -ea), a.umax[(int64_t)n * a.Pn + p]);
+                scatter_cs_slice<P, true>(F, lds, a.vecs[nb] + (int64_t)p * a.I[nb],
+                                          a.tab + (int64_t)d * a.sumI + a.off[nb], a.I[nb], a.J[nb], q, a.s,
+                                          ldexpf(1.0f, -eb), a.umax[(int64_t)nb * a.Pn + p]);
+                forward_regs<P>(lds, a.s.twP, F);
+                split_pair_product<P>(F, lds, q != 0, ea + eb);
+#pragma unroll
+                for (int e = 0; e < E; ++e) X[e] = cmulc(X[e], F[e]);
+                n = nb;
+                continue;
+            }
             if (a.umax && a.J[n] <= P) {
                 scatter_cs_slice<P>(F, lds, vn, a.tab + (int64_t)d * a.sumI + a.off[n], a.I[n], a.J[n], q, a.s,
                                     1.0f, a.umax[(int64_t)n * a.Pn + p]);
@@ -574,7 +595,7 @@ size_t fcs_ws_free_mode(const fcs_plan *p, int64_t Pn) {
         Imax = std::max<int64_t>(Imax, p->I[n]);
     }
     return align256((size_t)p->D * Pn * Jmax * 4) + align256((size_t)Pn * Imax * p->D * 4) +
-           align256((size_t)p->N * Pn * 4);
+           align256(2 * (size_t)p->N * Pn * 4);
 }
 
 // Argument checks shared by fcs_sketch_cp and fcs_sketch_cp_noalloc
@@ -823,9 +844,11 @@ extern "C" fcs_status fcs_contract_free_mode(fcs_plan_t p, const float *spec, in
     int64_t Imax = 0;
     for (int n = 0; n < p->N; ++n) Imax = std::max<int64_t>(Imax, p->I[n]);
     float *vmax = (float *)((char *)fa.est + align256((size_t)Pn * Imax * p->D * 4));
+    float *vexp = vmax + (int64_t)p->N * Pn;
     fa.umax = vmax;
+    fa.uexp = vexp;
     hipStream_t s = (hipStream_t)stream;
-    launch_column_absmax(fa.vecs, fa.I, p->N, (int)Pn, vmax, nullptr, s);
+    launch_column_absmax(fa.vecs, fa.I, p->N, (int)Pn, vmax, vexp, s);
     FCS_DISPATCH_FFT(p->P, (launch_free<PP>(fa, s)));
     FCS_LAUNCH_CHECK();
     const int64_t rows = Pn * p->I[free_mode];
