@@ -406,9 +406,11 @@ FCS_API fcs_status fcs_ts_fold(fcs_plan_t plan, const float *y, float *ts, void 
  *              (may be NULL), vecs[n] is P x I_n row-major float
  *   out        device, double, P x I_free row-major
  *   ws         device workspace of at least fcs_workspace_bytes(FCS_OP_FREE_MODE,
- *              0, P) bytes (z, the per-sketch estimates and the vector maxima)
+ *              0, P) bytes (z, the per-sketch estimates, the vector maxima
+ *              and norm exponents)
  * The count sketches of the vectors are formed as in fcs_sketch_cp (64-bit
- * fixed point scaled to each vector's maximum for J_n <= P).
+ * fixed point scaled to each vector's maximum for J_n <= P; two vectors
+ * share one transform on the conjugate-symmetric slices).
  * Errors: FCS_EINVAL, FCS_ENOMEM, FCS_EUNSUPPORTED, FCS_EDEVICE. */
 FCS_API fcs_status fcs_contract_free_mode(fcs_plan_t plan, const float *spec,
                                   int32_t free_mode, int64_t P,
