@@ -196,8 +196,9 @@ __device__ __forceinline__ void build_cs_slice(float2 (&wv)[Shape<P>::E], const 
 // reach 2^62, and added as an integer.  The sums are exact apart from the
 // truncation of each scaled entry to an integer (less than 2^-F, which is
 // at most 2^(ceil(log2 I_n) - 61) umax), and do not depend on the order of
-// the atomics; each bin is then read back through double precision and
-// rounded once to float.  A column with a non-finite entry (umax not
+// the atomics; each bin's 64-bit sum is then converted to float from its
+// two signed 32-bit halves (one fused multiply-add, within about one ulp)
+// and scaled back by 2^-F.  A column with a non-finite entry (umax not
 // finite) is summed with float atomics instead, so infinities and NaNs
 // reach the sketch as in a float sum.  The LDS must be free on entry (no
 // thread still reading it); it is free again on return.  IMAG adds i times
@@ -269,9 +270,12 @@ __device__ __forceinline__ void scatter_cs_slice(float2 (&wv)[Shape<P>::E], floa
         if (j >= Jn) {
             y[e] = 0.f;
         } else if (fixed) {
-            const unsigned long long b = bins[j];
-            const double v = fma((double)(int)(uint32_t)(b >> 32), 4294967296.0, (double)(uint32_t)b);
-            y[e] = (float)ldexp(v, -F);
+            // v = hi 2^32 + lo with lo the signed low word, so that
+            // |lo| <= 2^31 and a small negative sum keeps hi = 0 (|v| < 2^62)
+            const long long v = (long long)bins[j];
+            const int lo = (int)(uint32_t)v;
+            const int hi = (int)(v >> 32) + (int)((uint32_t)lo >> 31);
+            y[e] = ldexpf(fmaf((float)hi, 4294967296.0f, (float)lo), -F);
         } else {
             y[e] = fbins[j];
         }

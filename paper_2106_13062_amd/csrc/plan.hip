@@ -98,13 +98,33 @@ __global__ void hash_tables_kernel(HashArgs a) {
     a.tab[t] = (uint32_t)h | ((y & 1ull) ? FCS_S_BIT : 0u);
 }
 
-// exp(-2 pi i k / n) evaluated in double precision, stored as float.
-__global__ void twiddle_kernel(float2 *w, int64_t n) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    double s, c;
-    sincospi(-2.0 * (double)k / (double)n, &s, &c);
-    w[k] = make_float2((float)c, (float)s);
+// exp(-2 pi i k / n) in single precision.  The angle 2 pi k / n is reduced
+// exactly, in integers, to an octant o and a remainder r (8k = o n + r,
+// 0 <= r < n); sincospif gives the sine and cosine of pi r / (4n) (pi (n - r)
+// / (4n), the complement, in odd octants), and the quarter-turn symmetries
+// place them.  n <= 2^20, so 4n and r are exact in float and the argument
+// is rounded once.
+__global__ void twiddle_kernel(float2 *w, int64_t n64) {
+    const int64_t k64 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k64 >= n64) return;
+    const int n = (int)n64;
+    const int k = (int)k64;
+    const int o = (8 * k) / n;
+    const int r = 8 * k - o * n;
+    float sb, cb;      // sine and cosine of the angle past the quarter turn
+    if (o & 1) {
+        sincospif((float)(n - r) / (float)(4 * n), &cb, &sb);
+    } else {
+        sincospif((float)r / (float)(4 * n), &sb, &cb);
+    }
+    float c, s;
+    switch (o >> 1) {
+    case 0: c = cb; s = sb; break;
+    case 1: c = -sb; s = cb; break;
+    case 2: c = -cb; s = -sb; break;
+    default: c = sb; s = -cb; break;
+    }
+    w[k] = make_float2(c, -s);
 }
 
 __global__ void zero_fill_kernel(float4 *p4, int64_t n4, float *tail, int64_t ntail) {

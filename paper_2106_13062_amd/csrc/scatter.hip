@@ -608,10 +608,12 @@ __device__ __forceinline__ void dense_block(const DenseArgs &a, int64_t bid, uin
     uint32_t *ctl = rowtab + 4 * a.period;
     const int64_t c_lo = (int64_t)s0 * SEG;
     const int64_t c_hi = min<int64_t>((int64_t)s1 * SEG, a.I0);
-    const double nelem = (double)nrows * (double)(c_hi - c_lo);
+    // entries of the block (a count, in single precision for the error model)
+    const float nelem = (float)nrows * (float)(c_hi - c_lo);
     int F;
     if constexpr (EXACT) {
-        F = dense_exact_exponent<VEC4>(a, r0, r1, c_lo, c_hi, nelem, qbins, wave, lane);
+        F = dense_exact_exponent<VEC4>(a, r0, r1, c_lo, c_hi, (double)nrows * (double)(c_hi - c_lo), qbins, wave,
+                                       lane);
     } else {
         F = SCALE_TOP - 1;
         if (M0 > 0.f) F = SCALE_TOP - __builtin_amdgcn_frexp_expf(M0);
@@ -637,7 +639,7 @@ __device__ __forceinline__ void dense_block(const DenseArgs &a, int64_t bid, uin
         // range and the modelled rounding error is small beside every
         // window (the row loops ended at a barrier: the flag is final);
         // otherwise the block goes to the redo list of the exact kernel
-        if (*ctl != 0u || !dense_error_ok<DG>(nrm, (float)nelem, qbins, wave, lane)) {
+        if (*ctl != 0u || !dense_error_ok<DG>(nrm, nelem, qbins, wave, lane)) {
             if (threadIdx.x == 0) {
                 const uint32_t slot = atomicAdd(a.redo_n, 1u);
                 a.redo_list[slot] = (uint32_t)bid;
@@ -915,8 +917,7 @@ __global__ __launch_bounds__(COO_THREADS) void coo_scatter_kernel(CooArgs a) {
     if (M0 > 0.f) F = COO_TOP - __builtin_amdgcn_frexp_expf(M0);
     F = max(-100, min(100, F));
     const float scale = ldexpf(1.0f, F);
-    const double inv = ldexp(1.0, -F);
-    const float wrap = (float)ldexp(1.0, 32 - F);      // one wrap of a bin, in sketch units
+    const float wrap = ldexpf(1.0f, 32 - F);           // one wrap of a bin, in sketch units
 
     // U entries per thread per step: their coordinate and value loads are
     // all issued before any is used, and their returning atomics before any
@@ -1000,7 +1001,7 @@ __global__ __launch_bounds__(COO_THREADS) void coo_scatter_kernel(CooArgs a) {
         const int qv = (int)bins[k];
         if (qv != 0) {
             const int d = k / Jt;
-            unsafeAtomicAdd(a.out + (int64_t)(d0 + d) * a.Jt + (k - d * Jt), (float)((double)qv * inv));
+            unsafeAtomicAdd(a.out + (int64_t)(d0 + d) * a.Jt + (k - d * Jt), ldexpf((float)qv, -F));
         }
     }
 }
