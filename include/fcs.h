@@ -127,8 +127,13 @@ FCS_API size_t fcs_plan_table_bytes(fcs_plan_t plan);
  *   h_n(i) = ((y >> 32) * J_n) >> 32,     s_n(i) = (y & 1) ? -1 : +1,
  * where mix is the SplitMix64 output function (Steele, Lea, Flood 2014);
  * the paper asks only for 2-wise independent pairs (Definitions 1-4).
+ * Layout of the tables (each part starting at a 256-byte boundary): the
+ * packed hash words, uint32 [D][sum_n I_n] (bit 31 = sign s = -1, bits
+ * 0..30 = h_n(i)); the twiddles exp(-2 pi i k / P), float2 [P]; the
+ * twiddles exp(-2 pi i k / L), float2 [L]; then the inverse hash lists.
  * Twiddles are evaluated in single precision (exact integer reduction of
- * the angle to an octant, sincospif there; about 1.5 ulp at worst).
+ * the angle to an octant, sincospif there; about 1.5 ulp at worst, exact
+ * at the quarter turns).
  * Errors: FCS_EINVAL (null or misaligned buffer), FCS_EDEVICE. */
 FCS_API fcs_status fcs_plan_bind(fcs_plan_t plan, void *dev_tables, void *stream);
 

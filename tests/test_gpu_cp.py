@@ -218,6 +218,34 @@ def test_spectrum_layout_and_values(I, J, L):
             assert rel(X, F) <= TOL
 
 
+@pytest.mark.parametrize("I,J,L", [((100, 100, 100), (64, 64, 64), 0), ((50, 60), (300, 200), 0),
+                                   ((30, 40, 50), (700, 900, 1100), 3 * 1024),
+                                   ((10000, 10000, 10000), (16384, 16384, 16384), 0),
+                                   ((10000, 10000, 10000), (16384, 16384, 16384), 65536),
+                                   ((100, 100), (40000, 24000), 0)])
+def test_twiddle_tables(I, J, L):
+    """The plan's twiddle tables exp(-2 pi i k / P) and exp(-2 pi i k / L),
+    read back from the bound table memory (layout of fcs_plan_bind): within
+    2^-22 of the exact values per component (the argument's rounding and
+    sincospif's error, a few ulp), exact at the quarter turns."""
+    D = 2
+    plan = Plan(I, J, D, 5, L=L, device=DEV)
+    tb = plan.tables.cpu().numpy()
+    a256 = lambda x: (x + 255) // 256 * 256
+    offP = a256(D * sum(I) * 4)
+    offL = a256(offP + plan.P * 8)
+    print(f"I={I} J={J} L={plan.L} P={plan.P} Q={plan.Q}", flush=True)
+    for off, n in ((offP, plan.P), (offL, plan.L)):
+        w = tb[off:off + 8 * n].view(np.float32).reshape(n, 2).astype(np.float64)
+        k = np.arange(n)
+        ex = np.exp(-2j * np.pi * k / n)
+        err = np.maximum(np.abs(w[:, 0] - ex.real), np.abs(w[:, 1] - ex.imag))
+        assert err.max() <= 2.0 ** -22, (n, err.max(), int(err.argmax()))
+        if n % 4 == 0:
+            quarter = w[:: n // 4]
+            assert np.array_equal(quarter, [[1, 0], [0, -1], [-1, 0], [0, 1]]), quarter
+
+
 FREE_CASES = [
     # (I, J, D, P, free)
     ((30, 25, 20), (32, 32, 32), 5, 4, 0),
