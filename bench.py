@@ -954,6 +954,34 @@ def copy_ceiling_gbs(torch, dev, nbytes=1 << 30, reps=10):
     return 2.0 * nbytes / (ms * 1e-3) / 1e9
 
 
+def lds_atomic_ceiling(torch, dev, cfg, kernel_ms, reps=5):
+    """LDS-atomic ceiling of the dense scatter: fcs_probe_lds_atomics on the
+    dense kernel's grid (one 1024-thread workgroup per last-mode slab and
+    group of four sketches, every row of the slab adding its I_0 = 1024
+    columns to four windows of J_0 + J_1 - 1 bins), the same atomics with no
+    loads or conversions, timed with HIP events on the launch stream; with
+    random column bins and with conflict-free bins."""
+    from paper_2106_13062_amd.fcs import probe_lds_atomics
+    I, J = list(cfg.I), list(cfg.J)
+    rows = int(np.prod(I[1:-1]))
+    blocks = I[-1] * (cfg.D // 4)
+    window, span = J[0] + J[1] - 1, J[0]
+    stream = torch.cuda.current_stream()
+    sink = torch.empty(blocks, dtype=torch.int32, device=dev)
+    res = {"atomics_per_launch": blocks * rows * 1024 * 4, "kernel_ms": kernel_ms}
+    for name, pattern in (("random_bins", 0), ("conflict_free", 1)):
+        def fn():
+            probe_lds_atomics(blocks, rows, window, span, pattern, 1, sink=sink, stream=stream)
+        fn()
+        torch.cuda.synchronize()
+        ms, _ = event_timer(torch, stream, fn, reps)
+        if not bool((sink == rows * 4096).all().item()):
+            raise RuntimeError("LDS-atomic probe lost additions")
+        res[name + "_ms"] = ms
+        res["kernel_vs_" + name] = ms / kernel_ms
+    return res
+
+
 def copy_calibration(torch, dev, nbytes=1 << 30, reps=5):
     """A plain device-to-device copy of known size, for scaling the
     FETCH_SIZE / WRITE_SIZE counters of the profiled kernels."""
@@ -1176,6 +1204,7 @@ def main():
         return
     cfg, res, cpu, T = dense_workload(args, torch, dev)
     copy_gbs = copy_ceiling_gbs(torch, dev)
+    lds_ceiling = lds_atomic_ceiling(torch, dev, cfg, res["event_ms"])
     secondary = {}
     if args.mode == "full":
         import synth
@@ -1236,7 +1265,8 @@ def main():
                      "frac": res["achieved_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "dense_scatter_kernel", "launch_ms": res["event_ms"],
                      "alg_bytes_per_launch": res["alg_bytes"],
-                     "copy_ceiling": copy_gbs, "frac_of_copy_ceiling": res["achieved_gbs"] / copy_gbs},
+                     "copy_ceiling": copy_gbs, "frac_of_copy_ceiling": res["achieved_gbs"] / copy_gbs,
+                     "lds_atomic": lds_ceiling},
         "cpu_baseline": cpu,
         "secondary": secondary,
     }

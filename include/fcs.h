@@ -61,6 +61,7 @@ extern "C" {
 #define FCS_MAX_ORDER 8      /* largest supported order N                  */
 #define FCS_MAX_D 64         /* largest number of independent sketches D   */
 #define FCS_MAX_FFT 16384    /* largest LDS-resident FFT size P            */
+#define FCS_PROBE_MAX_WINDOW 10000  /* largest window of fcs_probe_lds_atomics */
 
 typedef enum {
     FCS_OK = 0,
@@ -529,6 +530,23 @@ FCS_API size_t fcs_als_workspace_bytes(int32_t R, int64_t In);
 FCS_API fcs_status fcs_als_update(int32_t R, int64_t In, const double *Mt, int32_t nother,
                           const float *const *others, const int64_t *Iother, float *Ft_out,
                           double *lam, void *ws, size_t ws_bytes, void *stream);
+
+/* Measurement probe, not an operation of the paper: the cost of the LDS
+ * atomics of the dense scatter (Section 3.2) alone, for comparison with
+ * fcs_sketch_dense on the same grid.  `blocks` workgroups of 1024 threads
+ * each add rows x 1024 columns x 4 windows of ones into four LDS windows of
+ * `window` 32-bit bins, bin h_d(c) + o_d(row) of window d, with 32-bit LDS
+ * atomics and no other memory traffic: h_d(c) in [0, span) from a counter
+ * hash of `seed` (pattern 0: random column bins, the bank conflicts of
+ * random hashes) or the 64 lanes of every atomic on consecutive bins
+ * (pattern 1: no bank conflicts); o_d(row) in [0, window - span],
+ * wave-uniform.  Every workgroup writes the sum of its bins, rows * 4096, to
+ * sink[block] (device, `blocks` uint32).  Asynchronous on `stream`.
+ * Errors: FCS_EINVAL (blocks < 1, rows outside [1, 2^20), pattern not 0 or
+ * 1, span < 1024, span > window, window > FCS_PROBE_MAX_WINDOW, null sink),
+ * FCS_EDEVICE. */
+FCS_API fcs_status fcs_probe_lds_atomics(int32_t blocks, int32_t rows, int32_t window, int32_t span,
+                                 int32_t pattern, uint32_t seed, uint32_t *sink, void *stream);
 
 /* Text of a status code (static storage). */
 FCS_API const char *fcs_status_str(fcs_status status);

@@ -73,6 +73,7 @@ SIGNATURES = {
     "fcs_normalize_rows": (I32, [I64, I64, P, P, P, P, P]),
     "fcs_select_max": (I32, [I64, P, I64, P, P, P, P, P, P]),
     "fcs_axpy": (I32, [I64, ctypes.c_float, P, P, P]),
+    "fcs_probe_lds_atomics": (I32, [I32, I32, I32, I32, I32, ctypes.c_uint32, P, P]),
     "fcs_als_workspace_bytes": (SZ, [I32, I64]),
     "fcs_als_update": (I32, [I32, I64, P, I32, ctypes.POINTER(P), ctypes.POINTER(I64), P, P, P, SZ, P]),
     "fcs_contract_free_mode": (I32, [P, P, I32, I64, ctypes.POINTER(P), P, P, SZ, P]),

@@ -503,3 +503,19 @@ def als_update(Mt: torch.Tensor, others, out=None, lam=None, ws=None, stream=Non
     C.check(lib.fcs_als_update(R, In, _ptr(Mt), len(others), ptrs, Is, _ptr(out), _ptr(lam), _ptr(ws),
                                ctypes.c_size_t(ws.numel() * ws.element_size()), _stream(stream)))
     return out, lam
+
+
+def probe_lds_atomics(blocks: int, rows: int, window: int, span: int, pattern: int, seed: int = 1,
+                      sink=None, device=None, stream=None) -> torch.Tensor:
+    """fcs_probe_lds_atomics: the LDS atomics of the dense scatter's access
+    pattern alone (a measurement probe); returns the per-workgroup bin sums
+    (uint32 as int32, each rows * 4096)."""
+    lib = C.load()
+    if sink is None:
+        sink = torch.empty(blocks, dtype=torch.int32, device=device)
+    _need(sink, torch.int32, "sink")
+    if sink.numel() < blocks:
+        raise ValueError("sink holds fewer than `blocks` entries")
+    C.check(lib.fcs_probe_lds_atomics(int(blocks), int(rows), int(window), int(span), int(pattern),
+                                      int(seed) & 0xFFFFFFFF, _ptr(sink), _stream(stream)))
+    return sink

@@ -146,3 +146,18 @@ def test_ts_fold_and_inner_median_validate_before_device_work():
     assert lib.fcs_inner_median(2, 0, x, x, x, None, None, 0, None) == L.FCS_EINVAL
     assert lib.fcs_inner_median(2, 10, x, x, x, None, None, 0, None) == L.FCS_EINVAL   # no workspace
     lib.fcs_plan_destroy(h)
+
+
+@pytest.mark.parametrize("args", [
+    (0, 4, 8191, 4096, 0), (4, 0, 8191, 4096, 0), (4, 1 << 20, 8191, 4096, 0),
+    (4, 4, 8191, 4096, 2), (4, 4, 8191, 1000, 0), (4, 4, 4000, 4096, 0), (4, 4, 10001, 4096, 0),
+])
+def test_probe_rejects_before_launch(args):
+    lib = F.load()
+    sink = ctypes.c_void_p(256)      # never dereferenced: the arguments are rejected first
+    assert lib.fcs_probe_lds_atomics(*args, 1, sink, None) == L.FCS_EINVAL
+    assert lib.fcs_last_error()
+
+
+def test_probe_rejects_null_sink():
+    assert F.load().fcs_probe_lds_atomics(4, 4, 8191, 4096, 0, 1, None, None) == L.FCS_EINVAL

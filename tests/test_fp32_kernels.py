@@ -30,6 +30,7 @@ FP32_ONLY = [
     "kron_kernel", "contraction_factor_kernel", "contraction_forward_kernel",
     "batch_kernel", "ts_fold_kernel",
     "twiddle_kernel", "hash_tables_kernel", "axpy_kernel",
+    "lds_atomic_probe_kernel",
 ]
 # final reductions and norms: double precision allowed
 FP64_ALLOWED = [
