@@ -982,6 +982,33 @@ def lds_atomic_ceiling(torch, dev, cfg, kernel_ms, reps=5):
     return res
 
 
+def lds_atomic_sweep(torch, dev, reps=5):
+    """fcs_probe_lds_atomics over window sizes at the dense1024 launch's
+    atomic count (2048 workgroups x 1024 rows x 4096 atomics): four
+    8191-bin windows fill LDS (one workgroup per CU, as in the dense
+    scatter); 4096 bins and below let two or more workgroups share a CU.
+    Rate = lanes added per clock and CU at 2.4 GHz."""
+    from paper_2106_13062_amd.fcs import probe_lds_atomics
+    stream = torch.cuda.current_stream()
+    blocks, rows = 2048, 1024
+    sink = torch.empty(blocks, dtype=torch.int32, device=dev)
+    out = []
+    for window, span in ((8191, 4096), (4096, 2048), (2048, 1024), (1024, 1024)):
+        for pattern in (0, 1):
+            def fn():
+                probe_lds_atomics(blocks, rows, window, span, pattern, 1, sink=sink, stream=stream)
+            fn()
+            torch.cuda.synchronize()
+            ms, _ = event_timer(torch, stream, fn, reps)
+            if not bool((sink == rows * 4096).all().item()):
+                raise RuntimeError("LDS-atomic probe lost additions")
+            lanes = blocks * rows * 4096 / (256 * ms * 1e-3 * 2.4e9)
+            out.append({"window": window, "span": span,
+                        "bins": "random" if pattern == 0 else "conflict-free",
+                        "ms": ms, "lanes_per_clock_per_cu": lanes})
+    return out
+
+
 def copy_calibration(torch, dev, nbytes=1 << 30, reps=5):
     """A plain device-to-device copy of known size, for scaling the
     FETCH_SIZE / WRITE_SIZE counters of the profiled kernels."""
@@ -1141,10 +1168,11 @@ def main():
                     help="rows of the tensor the CPU oracle sketches")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "dense1024_traffic.json"))
     ap.add_argument("--mode", default="full", choices=["full", "dense", "coo", "cp", "batch", "serve", "rtpm", "als", "decompress", "compare",
-                                                       "copy"],
+                                                       "copy", "lds"],
                     help="full: headline + secondary workloads; dense: headline only; cp: the CP "
                          "sketches and T(I,u,v) only; batch: the uneven batch only; serve: the "
-                         "serving loop only; copy: plain copy kernel for counter calibration")
+                         "serving loop only; copy: plain copy kernel for counter calibration; lds: "
+                         "LDS-atomic probe over window sizes")
     ap.add_argument("--batch-count", type=int, default=4096, help="instances of the uneven batch")
     ap.add_argument("--batch-reps", type=int, default=3, help="timed passes of each batch path")
     ap.add_argument("--no-tune", dest="tune", action="store_false", help="skip the batch autotuner")
@@ -1169,6 +1197,9 @@ def main():
 
     if args.mode == "copy":
         copy_calibration(torch, dev)
+        return
+    if args.mode == "lds":
+        print(json.dumps({"lds_atomic_sweep": lds_atomic_sweep(torch, dev)}), flush=True)
         return
     if args.mode == "batch":
         print(json.dumps({"batch": batch_workload(args, torch, dev)}), flush=True)
