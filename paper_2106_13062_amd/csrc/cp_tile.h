@@ -204,6 +204,59 @@ __device__ __forceinline__ void build_cs_slice(float2 (&wv)[Shape<P>::E], const 
 // thread still reading it); it is free again on return.  IMAG adds i times
 // the slice to wv instead of overwriting it (two real sequences packed into
 // one complex transform).
+// Entries i = t, t + T, ... of a factor column added to their buckets h_n(i)
+// with sign s_n(i): as 64-bit fixed point at scale 2^F (FIXED) or with float
+// atomics.  Each round issues the loads of K entries per thread before any
+// atomic; rounds whose K entries all exist skip the per-entry bounds test.
+template <int T, int K, bool FIXED>
+__device__ __forceinline__ void scatter_entries(float2 *lds, const float *__restrict__ u,
+                                                const uint32_t *__restrict__ words, int In, int F, int t) {
+    unsigned long long *bins = reinterpret_cast<unsigned long long *>(lds);
+    float *fbins = reinterpret_cast<float *>(lds);
+    auto add = [&](uint32_t w, float x) {
+        const uint32_t h = w & FCS_H_MASK;
+        const bool neg = (__float_as_uint(x) ^ w) & FCS_S_BIT;   // sign of s_n(i) u_i
+        if constexpr (FIXED) {
+            // |u_i| 2^F < 2^62 split into exact 32-bit halves, then negated
+            // as a 64-bit integer when s_n(i) u_i < 0
+            const float a = ldexpf(fabsf(x), F);
+            const float ahi = floorf(ldexpf(a, -32));
+            const float alo = fmaf(-ahi, 4294967296.0f, a);
+            unsigned long long v = ((unsigned long long)(uint32_t)ahi << 32) | (uint32_t)alo;
+            if (neg) v = 0ull - v;
+            __hip_atomic_fetch_add(bins + h, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        } else {
+            const float v = neg ? -fabsf(x) : fabsf(x);
+            __hip_atomic_fetch_add(fbins + h, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+    };
+    int i0 = t;
+    for (; i0 + (K - 1) * T < In; i0 += K * T) {
+        uint32_t w[K];
+        float x[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            w[k] = words[i0 + k * T];
+            x[k] = u[i0 + k * T];
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) add(w[k], x[k]);
+    }
+    if (i0 < In) {
+        uint32_t w[K];
+        float x[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int i = i0 + k * T;
+            w[k] = i < In ? words[i] : 0u;
+            x[k] = i < In ? u[i] : 0.f;
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            if (i0 + k * T < In) add(w[k], x[k]);
+    }
+}
+
 template <int P, bool IMAG = false>
 __device__ __forceinline__ void scatter_cs_slice(float2 (&wv)[Shape<P>::E], float2 *lds,
                                                  const float *__restrict__ u,
@@ -233,35 +286,8 @@ __device__ __forceinline__ void scatter_cs_slice(float2 (&wv)[Shape<P>::E], floa
         }
     }
     __syncthreads();
-    for (int i0 = t; i0 < In; i0 += K * T) {
-        uint32_t w[K];
-        float x[K];
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const int i = i0 + k * T;
-            w[k] = i < In ? words[i] : 0u;
-            x[k] = i < In ? u[i] : 0.f;
-        }
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            if (i0 + k * T >= In) continue;
-            const uint32_t h = w[k] & FCS_H_MASK;
-            const bool neg = (__float_as_uint(x[k]) ^ w[k]) & FCS_S_BIT;   // sign of s_n(i) u_i
-            if (fixed) {
-                // |u_i| 2^F < 2^62 split into exact 32-bit halves, then negated
-                // as a 64-bit integer when s_n(i) u_i < 0
-                const float a = ldexpf(fabsf(x[k]), F);
-                const float ahi = floorf(ldexpf(a, -32));
-                const float alo = fmaf(-ahi, 4294967296.0f, a);
-                unsigned long long v = ((unsigned long long)(uint32_t)ahi << 32) | (uint32_t)alo;
-                if (neg) v = 0ull - v;
-                __hip_atomic_fetch_add(bins + h, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            } else {
-                const float v = neg ? -fabsf(x[k]) : fabsf(x[k]);
-                __hip_atomic_fetch_add(fbins + h, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            }
-        }
-    }
+    if (fixed) scatter_entries<T, K, true>(lds, u, words, In, F, t);
+    else scatter_entries<T, K, false>(lds, u, words, In, F, t);
     __syncthreads();
     float y[E];
 #pragma unroll
