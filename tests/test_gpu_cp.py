@@ -52,6 +52,12 @@ CP_CASES = [
     ((60, 50, 40), (100, 90, 80), 4, 3, 65536),
     # order 5 on Q = 2: pairs (0, 1), (2, 3) and mode 4 alone
     ((12, 11, 10, 9, 8), (16, 16, 16, 16, 16), 3, 2, 32768),
+    # scatter rounds (8 entries per thread, 64 threads at P = 256, 1024 at
+    # P = 16384): exactly one full round, one full round and a one-entry
+    # tail, a tail that splits a wave, single entries
+    ((512, 513, 511), (64, 64, 64), 3, 2, 0),
+    ((1, 1023, 1025), (64, 64, 64), 2, 2, 0),
+    ((8192, 8193, 8191), (16384, 16384, 16384), 2, 2, 0),
 ]
 
 
